@@ -1,0 +1,153 @@
+#!/usr/bin/env python3
+"""Throughput of the plain BFAST Monitor path on one MI355X.
+
+Workload: one 1024 x 1024 tile (1,048,576 pixels), N = 400 FP32 observations,
+history n = 200, k = 3 harmonics (p = 8 regressors), h = 0.25 (H = 50),
+lambda = 2.5, f = 23, seeded synthetic season-trend series with 20% planted
+steps (see paper_1807_01751_amd/synth.py).  Y is device-resident before the
+timed region; one step is one bfm_fit_monitor call over the whole tile
+(fit, sigma, MOSUM, boundary test, break index and magnitude), FP64 arithmetic.
+
+Prints one JSON line.  Run with --gpus 1 (the default); more GPUs are not
+supported by this benchmark.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpixel/s at N=400,k=8 (plain vs mixed-precision); p50/p99 tile latency"
+P, N, n, ORDER, H_FRAC, LAM, FREQ = 1 << 20, 400, 200, 3, 0.25, 2.5, 23.0
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1807_01751_amd", "csrc", "plain_kernel.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plain_1024x1024_N400.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when the kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_sha():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(Y, seconds):
+    """The FP64 oracle on host cores over a bounded sample of the same tile."""
+    import numpy as np
+
+    from oracle import oracle
+    threads = oracle.threads(0)
+    probe = Y[:, :2048].cpu().numpy()
+    t0 = time.perf_counter()
+    oracle.fit_monitor(probe, n=n, order=ORDER, h=H_FRAC, lam=LAM, freq=FREQ, threads=threads,
+                       extras=False)
+    rate = probe.shape[1] / (time.perf_counter() - t0)
+    S = int(min(Y.shape[1], max(4096, rate * seconds)))
+    S -= S % 64
+    sample = np.ascontiguousarray(Y[:, :S].cpu().numpy())
+    t0 = time.perf_counter()
+    oracle.fit_monitor(sample, n=n, order=ORDER, h=H_FRAC, lam=LAM, freq=FREQ, threads=threads,
+                       extras=False)
+    dt = time.perf_counter() - t0
+    return {"value": S / dt / 1e6, "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {S} pixels of the same tile (all {N} observations each), "
+                      f"{dt:.1f} s on {threads} host threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the pixel-sharded multi-GPU form is described in DESIGN.md and not run here.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1807_01751_amd import bfm
+    from paper_1807_01751_amd.synth import make_series
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"bench: generating {P} x {N} series on {torch.cuda.get_device_name(dev)}")
+    Y, _ = make_series(P, N, n, ORDER, freq=FREQ, seed=2, device=dev)
+    out = {"brk": torch.empty(P, dtype=torch.int32, device=dev),
+           "mag": torch.empty(P, dtype=torch.float32, device=dev)}
+    torch.cuda.synchronize()
+
+    def step():
+        bfm.fit_monitor(Y, n=n, order=ORDER, freq=FREQ, h=H_FRAC, lam=LAM,
+                        outputs=("brk", "mag"), out_dtype=torch.float32, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"bench: warmup {args.warmup} done; timing {args.steps} steps")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    stream = torch.cuda.current_stream(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = sorted(a.elapsed_time(b) for a, b in ev)  # ms, per launch
+    ms_per_step = wall * 1e3 / args.steps
+    mean_lat = sum(lat) / len(lat)
+    p50 = lat[len(lat) // 2]
+    p99 = lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]
+    log(f"bench: {ms_per_step:.4f} ms/step wall, kernel mean {mean_lat:.4f} ms")
+
+    bytes_per_px = 4 * N + 4 + 4  # read FP32 y once; write int32 brk + FP32 mag
+    alg_bytes = bytes_per_px * P
+    achieved = alg_bytes / (mean_lat * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_per_launch(),
+            "kernel": "plain_kernel<8,false>", "algorithmic_bytes_per_launch": alg_bytes}
+    res = {"metric": METRIC, "value": round(P / (ms_per_step * 1e-3) / 1e6, 2), "unit": "Mpixel/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "plain BFAST Monitor, one 1024x1024 tile (1048576 pixels), "
+                                  "N=400 FP32 observations, n=200, k=3 harmonics (p=8), "
+                                  "h=0.25 (H=50), lambda=2.5, f=23, 20% planted steps",
+                      "pixels": P, "n_obs": N, "n_hist": n, "p": 2 + 2 * ORDER,
+                      "outputs": "brk int32 + mag f32", "parallelism": "single GPU"},
+           "p50_ms": round(p50, 5), "p99_ms": round(p99, 5), "roofline": roof}
+    if not args.no_cpu_baseline:
+        log("bench: timing the CPU oracle on a sample")
+        res["cpu_baseline"] = cpu_baseline(Y, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * bfm.h -- C ABI of libbfm, BFAST Monitor on AMD MI355X (gfx950).
+ *
+ * For every pixel of a stacked image time series the library fits the
+ * season-trend model of the paper (Eq. 1, written as the linear model of
+ * Eq. 2) on the stable history period by least squares (Eq. 5-6), forms the
+ * residuals and their scale (Algorithm 1, steps 3-5), the MOSUM of residuals
+ * over the monitoring period (Eq. 3), and tests it against the boundary of
+ * Eq. 4.  Each pixel yields its first break index, the MOSUM value of largest
+ * magnitude (the quantity mapped in the paper's Chile heat map, Section 4) and
+ * a status code.  The batched form of Section 3 (Eq. 7-11: one shared
+ * operator for all pixels) is what makes the GPU path a streaming pass.
+ *
+ * Conventions shared by every entry point:
+ *   - All array pointers are DEVICE pointers owned by the caller, except where
+ *     a comment says "host".  The library never frees them.
+ *   - Series are time-major (the N x m layout of Section 3): the observation
+ *     of pixel i at time t (t = 0..N-1, i.e. the paper's time t+1) is
+ *     Y[t*ld + i], with ld >= P.  Per-time optional outputs use ld = P.
+ *   - Functions return BFM_SUCCESS (0) or a negative BFM_E_* code; the text of
+ *     the last error of the calling thread is returned by bfm_last_error().
+ *   - Conditions of single pixels are not errors: they go to the per-pixel
+ *     status array (BFM_ST_*), and such pixels get brk = -1 and mag = NaN.
+ */
+#ifndef BFM_H
+#define BFM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BFM_VERSION 1
+
+/* return codes */
+#define BFM_SUCCESS 0
+#define BFM_E_INVAL (-1)       /* an argument violates the contract below   */
+#define BFM_E_LAYOUT (-2)      /* ld or ldv smaller than P                  */
+#define BFM_E_NOMEM (-3)       /* device or host allocation failed          */
+#define BFM_E_NODEVICE (-4)    /* no such HIP device                        */
+#define BFM_E_HIP (-5)         /* a HIP runtime call failed                 */
+#define BFM_E_UNSUPPORTED (-6) /* device is not gfx950, or option not built  */
+
+/* how missing observations are found (missing ones are dropped) */
+#define BFM_MASK_NONE 0     /* every observation is used; a non-finite one
+                               makes the pixel BFM_ST_NONFINITE            */
+#define BFM_MASK_NAN 1      /* an observation is used iff it is finite      */
+#define BFM_MASK_EXPLICIT 2 /* used iff valid[t*ldv+i] != 0; a non-finite
+                               used observation makes the pixel NONFINITE  */
+
+/* arithmetic of the computation */
+#define BFM_PREC_FP64 0
+
+/* element type of the floating-point outputs */
+#define BFM_OUT_F32 0
+#define BFM_OUT_F64 1
+
+/* per-pixel status */
+#define BFM_ST_OK 0
+#define BFM_ST_NONFINITE 1        /* NaN/Inf among the used observations     */
+#define BFM_ST_INSUFFICIENT 2     /* n_v <= p, or window H < 1 or H > n_v    */
+#define BFM_ST_RANK_DEFICIENT 3   /* history design rank deficient           */
+#define BFM_ST_DEGENERATE_SIGMA 4 /* sigma <= 1e-6 * max |y| over history    */
+#define BFM_ST_NO_MONITOR 5       /* no used observation after the history   */
+
+/*
+ * Method parameters (Algorithm 1 "Require" list; Section 2.1).
+ *   n_obs     N, series length, N > n_hist.
+ *   n_hist    n, length of the stable history period, 1 <= n < N.
+ *   order     k, number of harmonic terms (Eq. 1); p = 2 + 2k regressors,
+ *             0 <= k <= 8.
+ *   h_window  MOSUM bandwidth h as a count of observations (Eq. 3),
+ *             1 <= h_window <= n; 0 means "use h_frac".
+ *   freq      f, observations per year (Eq. 1), > 0.
+ *   h_frac    bandwidth as a fraction of the history: H = floor(h_frac * n)
+ *             (with missing values: floor(h_frac * n_v)); 0 < h_frac <= 1.
+ *   lambda    critical value of the boundary (Eq. 4), > 0.
+ *   mask_mode one of BFM_MASK_*.
+ *   precision BFM_PREC_FP64.
+ */
+typedef struct {
+    int32_t n_obs;
+    int32_t n_hist;
+    int32_t order;
+    int32_t h_window;
+    double freq;
+    double h_frac;
+    double lambda;
+    int32_t mask_mode;
+    int32_t precision;
+} bfm_params;
+
+/*
+ * Outputs, all caller-owned device pointers.  Only brk is required; any other
+ * pointer may be NULL.  Floating-point outputs have element type out_dtype.
+ *   brk     int32[P]: first monitoring index i (0 <= i < N-n, time n+1+i in
+ *           the paper's 1-based time) whose |MO| exceeds the boundary
+ *           (Algorithm 1, step 13), or -1.
+ *   mag     [P]: the MOSUM value of largest magnitude over the monitoring
+ *           period (hi = max MO, lo = min MO; mag = hi if hi >= -lo else lo).
+ *   sigma   [P]: residual scale of the history fit (Algorithm 1, step 5).
+ *   status  uint8[P]: BFM_ST_*.
+ *   beta    [p * P]: coefficients in the basis of Eq. 2, coefficient-major
+ *           (beta[j*P + i]) like beta_all of Eq. 8.
+ *   resid   [N * P]: residuals y - yhat (Eq. 11), time-major, NaN where an
+ *           observation is not used.
+ *   mosum   [(N-n) * P]: MO of Eq. 3, time-major, NaN where not defined.
+ */
+typedef struct {
+    int32_t *brk;
+    void *mag;
+    void *sigma;
+    uint8_t *status;
+    void *beta;
+    void *resid;
+    void *mosum;
+    int32_t out_dtype;
+} bfm_outputs;
+
+typedef struct bfm_ctx bfm_ctx;
+
+/* Library version (BFM_VERSION of the build). */
+int bfm_version(void);
+
+/* Text of the calling thread's last error ("" if none).  Owned by the library;
+ * valid until the thread's next call into the library. */
+const char *bfm_last_error(void);
+
+/*
+ * Validate parameters and layout without touching a device.
+ * Returns BFM_SUCCESS, BFM_E_INVAL or BFM_E_LAYOUT (ld < P).
+ */
+int bfm_check_params(const bfm_params *prm, int64_t P, int64_t ld);
+
+/*
+ * Create a context on HIP device `device`.  The context owns device copies of
+ * the shared operators (built once per parameter set; Section 3 builds the
+ * shared matrix M once for all pixels) and releases them in bfm_destroy.  One
+ * context may be used by one host thread at a time.
+ * Errors: BFM_E_INVAL (out NULL), BFM_E_NODEVICE, BFM_E_UNSUPPORTED (not
+ * gfx950), BFM_E_HIP.
+ */
+int bfm_create(bfm_ctx **out, int device);
+
+/* Release a context and its device memory.  NULL is accepted. */
+int bfm_destroy(bfm_ctx *ctx);
+
+/*
+ * BFAST Monitor over P pixels (Algorithm 1 for every pixel; Section 3 batched
+ * form).
+ *   Y      device, float32, time-major, Y[t*ld + i], t < N, i < P, ld >= P.
+ *   valid  device, uint8, valid[t*ldv + i]; read only when mask_mode is
+ *          BFM_MASK_EXPLICIT, else may be NULL; ldv >= P.
+ *   out    host struct of device output pointers (see bfm_outputs).
+ *   stream hipStream_t on which all work is enqueued; the call returns
+ *          without waiting for it, except that the first call with a new
+ *          parameter set builds the shared operators on the host and copies
+ *          them to the device synchronously (tens of KB, once per set).
+ * P == 0 is accepted and does nothing (Y and the output pointers may then be
+ * NULL).
+ * Errors: BFM_E_INVAL (NULL ctx/prm/Y/out/out->brk, bad parameters, bad
+ * out_dtype), BFM_E_LAYOUT, BFM_E_NOMEM, BFM_E_HIP.
+ */
+int bfm_fit_monitor(bfm_ctx *ctx, const bfm_params *prm, const float *Y, int64_t P,
+                    int64_t ld, const uint8_t *valid, int64_t ldv, const bfm_outputs *out,
+                    void *stream);
+
+/*
+ * Host-only view of the shared operators the plain path streams against, for
+ * inspection and tests (no device needed).  With p = 2 + 2k, M = N - n:
+ *   q     host double[N * p]: row t is q_t = R^-T x~_t, where x~_t is the
+ *         design row of Eq. 2 with the trend written as (t - (n+1)/2)/n and
+ *         X~_n = Q R is the QR factorisation of the history rows; rows
+ *         0..n-1 are orthonormal columns spanning the history design.
+ *   w     host double[M * p]: w_t = sum of q_s over the MOSUM window of
+ *         monitoring time t (Eq. 3 window, H rows ending at t).
+ *   bnd   host double[M]: boundary of Eq. 4 at each monitoring time.
+ *   bmap  host double[p * p], row-major: beta (basis of Eq. 2) =
+ *         bmap * (Q' y_n), for the uncentred series.
+ * Any pointer may be NULL.  Returns BFM_E_INVAL on bad parameters, or
+ * BFM_E_UNSUPPORTED if the history design is rank deficient (then every pixel
+ * of a plain call gets BFM_ST_RANK_DEFICIENT).
+ */
+int bfm_host_operators(const bfm_params *prm, double *q, double *w, double *bnd, double *bmap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BFM_H */

@@ -1,0 +1,209 @@
+"""Python binding of libbfm (include/bfm.h): argument marshalling only.
+
+Every step of BFAST Monitor runs in the HIP kernels of ``libbfm.so``; this
+module passes torch tensors' device pointers and the current HIP stream through
+ctypes.  PyTorch provides device memory and streams, nothing else.  If the
+shared library is missing the import of the functions below fails loudly: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libbfm.so")
+
+# include/bfm.h constants
+SUCCESS = 0
+E_INVAL, E_LAYOUT, E_NOMEM, E_NODEVICE, E_HIP, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
+MASK_NONE, MASK_NAN, MASK_EXPLICIT = 0, 1, 2
+PREC_FP64 = 0
+OUT_F32, OUT_F64 = 0, 1
+ST_OK, ST_NONFINITE, ST_INSUFFICIENT, ST_RANK_DEFICIENT, ST_DEGENERATE_SIGMA, ST_NO_MONITOR = range(6)
+
+_ERRNAMES = {E_INVAL: "BFM_E_INVAL", E_LAYOUT: "BFM_E_LAYOUT", E_NOMEM: "BFM_E_NOMEM",
+             E_NODEVICE: "BFM_E_NODEVICE", E_HIP: "BFM_E_HIP", E_UNSUPPORTED: "BFM_E_UNSUPPORTED"}
+
+# Every symbol include/bfm.h declares.
+EXPORTS = ("bfm_version", "bfm_last_error", "bfm_check_params", "bfm_create", "bfm_destroy",
+           "bfm_fit_monitor", "bfm_host_operators")
+
+
+class BfmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("n_obs", ctypes.c_int32),
+        ("n_hist", ctypes.c_int32),
+        ("order", ctypes.c_int32),
+        ("h_window", ctypes.c_int32),
+        ("freq", ctypes.c_double),
+        ("h_frac", ctypes.c_double),
+        ("lambda_", ctypes.c_double),
+        ("mask_mode", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+    ]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [
+        ("brk", ctypes.c_void_p),
+        ("mag", ctypes.c_void_p),
+        ("sigma", ctypes.c_void_p),
+        ("status", ctypes.c_void_p),
+        ("beta", ctypes.c_void_p),
+        ("resid", ctypes.c_void_p),
+        ("mosum", ctypes.c_void_p),
+        ("out_dtype", ctypes.c_int32),
+    ]
+
+
+_lib = None
+_lock = threading.Lock()
+_ctx = {}
+
+
+def load():
+    """Load libbfm.so (built by ``python -m paper_1807_01751_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1807_01751_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    P_ = ctypes.POINTER(Params)
+    lib.bfm_version.restype = ctypes.c_int
+    lib.bfm_last_error.restype = ctypes.c_char_p
+    lib.bfm_check_params.argtypes = [P_, i64, i64]
+    lib.bfm_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+    lib.bfm_destroy.argtypes = [vp]
+    lib.bfm_fit_monitor.argtypes = [vp, P_, vp, i64, i64, vp, i64, ctypes.POINTER(Outputs), vp]
+    lib.bfm_host_operators.argtypes = [P_, vp, vp, vp, vp]
+    _lib = lib
+    return lib
+
+
+def _raise(rc):
+    if rc != SUCCESS:
+        raise BfmError(rc, load().bfm_last_error().decode())
+
+
+def version() -> int:
+    return load().bfm_version()
+
+
+def make_params(N: int, n: int, order: int = 3, freq: float = 23.0, h: float = 0.25,
+                h_window: int = 0, lam: float = 2.5, mask_mode: int = MASK_NONE) -> Params:
+    return Params(int(N), int(n), int(order), int(h_window), float(freq), float(h), float(lam),
+                  int(mask_mode), PREC_FP64)
+
+
+def check_params(prm: Params, P: int, ld: int) -> None:
+    """bfm_check_params: validation only, no device."""
+    _raise(load().bfm_check_params(ctypes.byref(prm), int(P), int(ld)))
+
+
+def host_operators(prm: Params):
+    """bfm_host_operators: the shared operators as float64 tensors (host only)."""
+    N, n, p = prm.n_obs, prm.n_hist, 2 + 2 * prm.order
+    q = torch.empty(N, p, dtype=torch.float64)
+    w = torch.empty(N - n, p, dtype=torch.float64)
+    bnd = torch.empty(N - n, dtype=torch.float64)
+    bmap = torch.empty(p, p, dtype=torch.float64)
+    rc = load().bfm_host_operators(ctypes.byref(prm), q.data_ptr(), w.data_ptr(), bnd.data_ptr(),
+                                   bmap.data_ptr())
+    _raise(rc)
+    return q, w, bnd, bmap
+
+
+def create(device: int) -> int:
+    """bfm_create: returns an opaque context handle."""
+    h = ctypes.c_void_p()
+    _raise(load().bfm_create(ctypes.byref(h), int(device)))
+    return h.value
+
+
+def destroy(ctx: int) -> None:
+    _raise(load().bfm_destroy(ctx))
+
+
+def context(device: int) -> int:
+    """A per-process context for ``device``, created on first use."""
+    with _lock:
+        if device not in _ctx:
+            _ctx[device] = create(device)
+        return _ctx[device]
+
+
+def _series_layout(Y: torch.Tensor):
+    """Accept Y as (N, P) time-major contiguous, or its (P, N) transpose view."""
+    if Y.dim() != 2:
+        raise ValueError("Y must be 2-D")
+    if Y.stride(1) == 1 and Y.stride(0) >= Y.shape[1]:
+        return Y, Y.shape[0], Y.shape[1], Y.stride(0)  # (N, P) with row stride ld
+    if Y.stride(0) == 1 and Y.stride(1) >= Y.shape[0]:
+        return Y, Y.shape[1], Y.shape[0], Y.stride(1)  # (P, N) view of a time-major block
+    raise ValueError("Y must be time-major: an (N, P) tensor with unit pixel stride, or its "
+                     "transpose; make a time-major copy with Y.t().contiguous()")
+
+
+def fit_monitor(Y: torch.Tensor, *, n: int, order: int = 3, freq: float = 23.0, h: float = 0.25,
+                h_window: int = 0, lam: float = 2.5, mask_mode: int = MASK_NONE,
+                valid: torch.Tensor | None = None, outputs=("brk", "mag"),
+                out_dtype: torch.dtype = torch.float64, out: dict | None = None,
+                stream: torch.cuda.Stream | None = None) -> dict:
+    """bfm_fit_monitor on a device-resident float32 series block.
+
+    ``Y`` is time-major: shape (N, P) with unit stride along pixels (or the
+    (P, N) transpose view of such a block).  ``outputs`` names the arrays to
+    produce among brk, mag, sigma, status, beta, resid, mosum; ``out`` may supply
+    preallocated tensors for them.  Work is enqueued on ``stream`` (default: the
+    current stream) and the call returns without synchronising.
+    """
+    if Y.dtype != torch.float32 or Y.device.type != "cuda":
+        raise ValueError("Y must be a float32 tensor on a HIP device")
+    Y, N, P, ld = _series_layout(Y)
+    dev = Y.device.index if Y.device.index is not None else torch.cuda.current_device()
+    prm = make_params(N, n, order, freq, h, h_window, lam, mask_mode)
+    p = 2 + 2 * order
+    shapes = {"brk": ((P,), torch.int32), "mag": ((P,), out_dtype), "sigma": ((P,), out_dtype),
+              "status": ((P,), torch.uint8), "beta": ((p, P), out_dtype),
+              "resid": ((N, P), out_dtype), "mosum": ((N - n, P), out_dtype)}
+    if out_dtype not in (torch.float32, torch.float64):
+        raise ValueError("out_dtype must be float32 or float64")
+    res = dict(out or {})
+    for name in set(outputs) | {"brk"}:
+        if name not in shapes:
+            raise ValueError(f"unknown output {name}")
+        shp, dt = shapes[name]
+        t = res.get(name)
+        if t is None:
+            res[name] = torch.empty(shp, dtype=dt, device=Y.device)
+        elif tuple(t.shape) != shp or t.dtype != dt or not t.is_contiguous() or t.device != Y.device:
+            raise ValueError(f"out[{name!r}] must be a contiguous {dt} tensor of shape {shp}")
+    o = Outputs(*(res[k].data_ptr() if k in res else None
+                  for k in ("brk", "mag", "sigma", "status", "beta", "resid", "mosum")),
+                OUT_F64 if out_dtype == torch.float64 else OUT_F32)
+    vptr, ldv = None, 0
+    if mask_mode == MASK_EXPLICIT:
+        if valid is None:
+            raise ValueError("valid is required with MASK_EXPLICIT")
+        valid, Nv, Pv, ldv = _series_layout(valid)
+        if (Nv, Pv) != (N, P) or valid.dtype != torch.uint8 or valid.device != Y.device:
+            raise ValueError("valid must be a uint8 tensor laid out like Y")
+        vptr = valid.data_ptr()
+    s = stream if stream is not None else torch.cuda.current_stream(Y.device)
+    rc = load().bfm_fit_monitor(context(dev), ctypes.byref(prm), Y.data_ptr(), P, ld, vptr, ldv,
+                                ctypes.byref(o), s.cuda_stream)
+    _raise(rc)
+    return res

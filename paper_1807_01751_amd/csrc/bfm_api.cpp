@@ -1,0 +1,246 @@
+// C ABI of libbfm: argument validation, contexts, the per-parameter-set cache of
+// shared operators, and dispatch to the gfx950 kernels.  Declarations and the
+// contract of every entry point are in include/bfm.h.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "bfm_internal.hpp"
+
+struct bfm_ctx {
+    int device = 0;
+    size_t max_lds = 0;  // dynamic LDS bytes one workgroup may use
+    std::mutex mu;
+    struct Entry {
+        bfm::PlainOps ops;
+        double* dev = nullptr;  // q | w | bnd | bmap
+    };
+    using Key = std::tuple<int, int, int, int, double, double, double>;
+    std::map<Key, Entry> plain;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(e == hipErrorOutOfMemory ? BFM_E_NOMEM : BFM_E_HIP, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+int check(const bfm_params* prm, int64_t P, int64_t ld)
+{
+    if (!prm) return fail(BFM_E_INVAL, "params is NULL");
+    const bfm_params& p = *prm;
+    if (p.n_hist < 1) return fail(BFM_E_INVAL, "n_hist must be >= 1 (got %d)", p.n_hist);
+    if (p.n_obs <= p.n_hist)
+        return fail(BFM_E_INVAL, "n_obs (%d) must exceed n_hist (%d)", p.n_obs, p.n_hist);
+    if (p.order < 0 || p.order > bfm::kMaxOrder)
+        return fail(BFM_E_INVAL, "order must be in [0, %d] (got %d)", bfm::kMaxOrder, p.order);
+    if (!(p.freq > 0) || !std::isfinite(p.freq))
+        return fail(BFM_E_INVAL, "freq must be positive and finite");
+    if (!(p.lambda > 0) || !std::isfinite(p.lambda))
+        return fail(BFM_E_INVAL, "lambda must be positive and finite");
+    if (p.h_window < 0 || p.h_window > p.n_hist)
+        return fail(BFM_E_INVAL, "h_window must be in [0, n_hist] (got %d)", p.h_window);
+    if (p.h_window == 0 && !(p.h_frac > 0 && p.h_frac <= 1))
+        return fail(BFM_E_INVAL, "h_frac must be in (0, 1] when h_window is 0");
+    if (p.mask_mode < BFM_MASK_NONE || p.mask_mode > BFM_MASK_EXPLICIT)
+        return fail(BFM_E_INVAL, "unknown mask_mode %d", p.mask_mode);
+    if (p.precision != BFM_PREC_FP64)
+        return fail(BFM_E_INVAL, "unknown precision %d", p.precision);
+    if (P < 0) return fail(BFM_E_INVAL, "P must be >= 0");
+    if (P > ((int64_t)1 << 30)) return fail(BFM_E_INVAL, "P must be <= 2^30 per call");
+    if (ld < P) return fail(BFM_E_LAYOUT, "ld (%lld) must be >= P (%lld)", (long long)ld, (long long)P);
+    g_err.clear();
+    return BFM_SUCCESS;
+}
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int bfm_version(void) { return BFM_VERSION; }
+
+const char* bfm_last_error(void) { return g_err.c_str(); }
+
+int bfm_check_params(const bfm_params* prm, int64_t P, int64_t ld) { return check(prm, P, ld); }
+
+int bfm_create(bfm_ctx** out, int device)
+{
+    if (!out) return fail(BFM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) return fail(BFM_E_NODEVICE, "no HIP device");
+    if (device < 0 || device >= count)
+        return fail(BFM_E_NODEVICE, "device %d out of range [0, %d)", device, count);
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess)
+        return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(BFM_E_UNSUPPORTED, "device %d is %s; libbfm is built for gfx950", device,
+                    prop.gcnArchName);
+    bfm_ctx* ctx = new (std::nothrow) bfm_ctx;
+    if (!ctx) return fail(BFM_E_NOMEM, "context allocation failed");
+    ctx->device = device;
+    ctx->max_lds = prop.sharedMemPerBlock;
+    *out = ctx;
+    g_err.clear();
+    return BFM_SUCCESS;
+}
+
+int bfm_destroy(bfm_ctx* ctx)
+{
+    if (!ctx) return BFM_SUCCESS;
+    {
+        DeviceGuard g(ctx->device);
+        for (auto& kv : ctx->plain)
+            if (kv.second.dev) (void)hipFree(kv.second.dev);
+    }
+    delete ctx;
+    return BFM_SUCCESS;
+}
+
+int bfm_host_operators(const bfm_params* prm, double* q, double* w, double* bnd, double* bmap)
+{
+    int rc = check(prm, 0, 0);
+    if (rc) return rc;
+    bfm::PlainOps ops;
+    bfm::build_plain_ops(*prm, &ops);
+    if (q) std::memcpy(q, ops.q.data(), ops.q.size() * sizeof(double));
+    if (w) std::memcpy(w, ops.w.data(), ops.w.size() * sizeof(double));
+    if (bnd) std::memcpy(bnd, ops.bnd.data(), ops.bnd.size() * sizeof(double));
+    if (bmap) std::memcpy(bmap, ops.bmap.data(), ops.bmap.size() * sizeof(double));
+    if (ops.n <= ops.p) return fail(BFM_E_INVAL, "n_hist (%d) must exceed p (%d)", ops.n, ops.p);
+    if (ops.H < 1) return fail(BFM_E_INVAL, "window length is < 1");
+    if (!ops.rank_ok) return fail(BFM_E_UNSUPPORTED, "history design is rank deficient");
+    return BFM_SUCCESS;
+}
+
+int bfm_fit_monitor(bfm_ctx* ctx, const bfm_params* prm, const float* Y, int64_t P, int64_t ld,
+                    const uint8_t* valid, int64_t ldv, const bfm_outputs* out, void* stream)
+{
+    if (!ctx) return fail(BFM_E_INVAL, "ctx is NULL");
+    int rc = check(prm, P, ld);
+    if (rc) return rc;
+    if (!out) return fail(BFM_E_INVAL, "out is NULL");
+    if (P == 0) return BFM_SUCCESS;
+    if (!Y || !out->brk) return fail(BFM_E_INVAL, "Y and out->brk are required");
+    if (out->out_dtype != BFM_OUT_F32 && out->out_dtype != BFM_OUT_F64)
+        return fail(BFM_E_INVAL, "unknown out_dtype %d", out->out_dtype);
+    if (prm->mask_mode == BFM_MASK_EXPLICIT) {
+        if (!valid) return fail(BFM_E_INVAL, "valid is required with BFM_MASK_EXPLICIT");
+        if (ldv < P) return fail(BFM_E_LAYOUT, "ldv must be >= P");
+    }
+    if (prm->mask_mode != BFM_MASK_NONE)
+        return fail(BFM_E_UNSUPPORTED, "masked path not available in this build");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bfm_params& p = *prm;
+    const int np = 2 + 2 * p.order;
+
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    DeviceGuard g(ctx->device);
+    bfm_ctx::Key key{p.n_obs, p.n_hist, p.order, p.h_window, p.freq, p.h_frac, p.lambda};
+    auto it = ctx->plain.find(key);
+    if (it == ctx->plain.end()) {
+        bfm_ctx::Entry ent;
+        bfm::build_plain_ops(p, &ent.ops);
+        const size_t nq = ent.ops.q.size(), nw = ent.ops.w.size(), nb = ent.ops.bnd.size(),
+                     nm = ent.ops.bmap.size();
+        std::vector<double> host;
+        host.reserve(nq + nw + nb + nm);
+        host.insert(host.end(), ent.ops.q.begin(), ent.ops.q.end());
+        host.insert(host.end(), ent.ops.w.begin(), ent.ops.w.end());
+        host.insert(host.end(), ent.ops.bnd.begin(), ent.ops.bnd.end());
+        host.insert(host.end(), ent.ops.bmap.begin(), ent.ops.bmap.end());
+        hipError_t e = hipMalloc(&ent.dev, host.size() * sizeof(double));
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(operators)");
+        // A synchronous copy: the operator block is a few tens of KB and this
+        // happens once per parameter set.
+        e = hipMemcpy(ent.dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(ent.dev);
+            return hip_fail(e, "hipMemcpy(operators)");
+        }
+        it = ctx->plain.emplace(key, std::move(ent)).first;
+    }
+    const bfm::PlainOps& ops = it->second.ops;
+
+    uint8_t global_st = BFM_ST_OK;
+    if (ops.n <= ops.p || ops.H < 1)
+        global_st = BFM_ST_INSUFFICIENT;
+    else if (!ops.rank_ok)
+        global_st = BFM_ST_RANK_DEFICIENT;
+    hipError_t e;
+    if (global_st != BFM_ST_OK) {
+        e = bfm::launch_fill_status(Y, ld, P, p.n_obs, p.n_hist, np, global_st, *out, p.mask_mode,
+                                    valid, ldv, s);
+        return e == hipSuccess ? BFM_SUCCESS : hip_fail(e, "fill_status launch");
+    }
+    const size_t lds = (size_t)ops.H * bfm::kPlainBlock * sizeof(float);
+    if (lds > ctx->max_lds)
+        return fail(BFM_E_UNSUPPORTED, "window H=%d needs %zu B of LDS per workgroup (max %zu)",
+                    ops.H, lds, ctx->max_lds);
+    const double* d = it->second.dev;
+    const size_t nq = ops.q.size(), nw = ops.w.size(), nb = ops.bnd.size();
+    bfm::PlainArgs a{};
+    a.Y = Y;
+    a.ld = ld;
+    a.P = P;
+    a.q = d;
+    a.w = d + nq;
+    a.bnd = d + nq + nw;
+    a.bmap = d + nq + nw + nb;
+    a.N = p.n_obs;
+    a.n = p.n_hist;
+    a.H = ops.H;
+    a.sqrt_n = std::sqrt((double)p.n_hist);
+    a.inv_dof = 1.0 / (double)(p.n_hist - np);
+    a.brk = out->brk;
+    a.mag = out->mag;
+    a.sigma = out->sigma;
+    a.status = out->status;
+    a.beta = out->beta;
+    a.resid = out->resid;
+    a.mosum = out->mosum;
+    a.out_f64 = out->out_dtype == BFM_OUT_F64;
+    e = bfm::launch_plain(a, np, s);
+    if (e != hipSuccess) return hip_fail(e, "plain kernel launch");
+    return BFM_SUCCESS;
+}
+
+}  // extern "C"

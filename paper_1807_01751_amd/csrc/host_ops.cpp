@@ -1,0 +1,153 @@
+// Host-side construction of the shared operators of the plain path (FP64).
+//
+// Section 3 of the paper observes that the pseudo-inverse of the history
+// design, M = (X_n X_n')^-1 X_n (Eq. 7), is the same for every pixel, so the
+// per-pixel fit collapses to one contraction with Y (Eq. 8).  This file builds
+// the orthonormal form of that operator once per parameter set:
+//
+//   x~_t  design row of Eq. 2 with the trend written (t - (n+1)/2) / n, which
+//         spans the same column space as (1, t) and keeps the factorisation
+//         well conditioned;
+//   X~_n = Q R (Householder, rows t = 1..n).  For history rows q_t is row t
+//         of the explicitly formed Q (orthonormal to rounding whatever the
+//         conditioning); for monitoring rows q_t = R^-T x~_t, the same map
+//         extended past the history.  Q' y_n = sum_t q_t y_t gives coordinates
+//         b' with yhat_t = q_t' b' and RSS = ||y_n||^2 - ||b'||^2;
+//   w_t   sum of q_s over the MOSUM window of monitoring time t, so the window
+//         sum of fitted values in Eq. 3 is w_t' b';
+//   bnd   the boundary of Eq. 4 at each monitoring time;
+//   bmap  maps b' back to beta in the basis of Eq. 2.
+#include <cmath>
+#include <cstring>
+
+#include "bfm_internal.hpp"
+
+namespace bfm {
+
+int window_length(const bfm_params& prm, int count)
+{
+    if (prm.h_window > 0) return prm.h_window;
+    return (int)std::floor(prm.h_frac * (double)count);
+}
+
+// Design row of Eq. 2 in the centred-trend basis, 1-based time t.  The angle is
+// reduced exactly (fmod is exact in IEEE arithmetic) before scaling by 2 pi/f.
+static void design_row_centred(int t, int n, int k, double f, double* x)
+{
+    x[0] = 1.0;
+    x[1] = ((double)t - 0.5 * (double)(n + 1)) / (double)n;
+    for (int j = 1; j <= k; ++j) {
+        double ang = (2.0 * M_PI / f) * std::fmod((double)j * (double)t, f);
+        x[2 * j] = std::sin(ang);
+        x[2 * j + 1] = std::cos(ang);
+    }
+}
+
+static double log_plus(double x) { return x <= M_E ? 1.0 : std::log(x); }
+
+bool build_plain_ops(const bfm_params& prm, PlainOps* ops)
+{
+    const int N = prm.n_obs, n = prm.n_hist, k = prm.order, p = 2 + 2 * k;
+    const int M = N - n;
+    const int H = window_length(prm, n);
+    ops->N = N;
+    ops->n = n;
+    ops->p = p;
+    ops->H = H;
+    ops->rank_ok = false;
+    ops->q.assign((size_t)N * p, 0.0);
+    ops->w.assign((size_t)M * p, 0.0);
+    ops->bnd.assign(M, 0.0);
+    ops->bmap.assign((size_t)p * p, 0.0);
+    for (int m = 0; m < M; ++m)
+        ops->bnd[m] = prm.lambda * std::sqrt(log_plus((double)(n + 1 + m) / (double)n));
+    if (n <= p) return true;  // every pixel INSUFFICIENT; no factorisation
+
+    // Householder QR of X~_n (n x p, column-major copy).
+    std::vector<double> A((size_t)n * p), x(p);
+    for (int t = 1; t <= n; ++t) {
+        design_row_centred(t, n, k, prm.freq, x.data());
+        for (int j = 0; j < p; ++j) A[(size_t)j * n + (t - 1)] = x[j];
+    }
+    std::vector<double> R((size_t)p * p, 0.0);
+    const double tol = kRankTol * std::sqrt((double)n);
+    bool ok = true;
+    for (int j = 0; j < p && ok; ++j) {
+        double* a = &A[(size_t)j * n];
+        double nrm = 0.0;
+        for (int i = j; i < n; ++i) nrm += a[i] * a[i];
+        nrm = std::sqrt(nrm);
+        if (nrm <= tol) {
+            ok = false;
+            break;
+        }
+        double rjj = a[j] > 0 ? -nrm : nrm;
+        a[j] -= rjj;
+        double vv = 0.0;
+        for (int i = j; i < n; ++i) vv += a[i] * a[i];
+        for (int c = j + 1; c < p; ++c) {
+            double* b = &A[(size_t)c * n];
+            double d = 0.0;
+            for (int i = j; i < n; ++i) d += a[i] * b[i];
+            d = 2.0 * d / vv;
+            for (int i = j; i < n; ++i) b[i] -= d * a[i];
+            R[(size_t)j * p + c] = b[j];
+        }
+        R[(size_t)j * p + j] = rjj;
+    }
+    if (!ok) return true;  // rank deficient: every pixel RANK_DEFICIENT
+    ops->rank_ok = true;
+
+    // History rows: Q = H_0 H_1 ... H_{p-1} [I_p; 0], reflectors stored in A
+    // below the diagonal (v_j = A[j.., j], H_j = I - 2 v v' / v'v).
+    for (int c = 0; c < p; ++c) {
+        std::vector<double> e(n, 0.0);
+        e[c] = 1.0;
+        for (int j = p - 1; j >= 0; --j) {
+            const double* a = &A[(size_t)j * n];
+            double vv = 0.0, d = 0.0;
+            for (int i = j; i < n; ++i) {
+                vv += a[i] * a[i];
+                d += a[i] * e[i];
+            }
+            d = 2.0 * d / vv;
+            for (int i = j; i < n; ++i) e[i] -= d * a[i];
+        }
+        for (int t = 0; t < n; ++t) ops->q[(size_t)t * p + c] = e[t];
+    }
+    // Monitoring rows: q_t = R^-T x~_t (forward substitution with R').
+    for (int t = n + 1; t <= N; ++t) {
+        design_row_centred(t, n, k, prm.freq, x.data());
+        double* qt = &ops->q[(size_t)(t - 1) * p];
+        for (int j = 0; j < p; ++j) {
+            double s = x[j];
+            for (int c = 0; c < j; ++c) s -= R[(size_t)c * p + j] * qt[c];
+            qt[j] = s / R[(size_t)j * p + j];
+        }
+    }
+    // w_t: window of Eq. 3 ending at monitoring time t (0-based t = n + m).
+    for (int m = 0; m < M; ++m) {
+        int t = n + m;
+        double* wt = &ops->w[(size_t)m * p];
+        for (int s = t - H + 1; s <= t; ++s)
+            for (int j = 0; j < p; ++j) wt[j] += ops->q[(size_t)s * p + j];
+    }
+    // bmap = T' R^-1, where x~ = T x: beta~ = R^-1 b', beta = T' beta~.
+    std::vector<double> Ri((size_t)p * p, 0.0);
+    for (int c = 0; c < p; ++c) {  // column c of R^-1 solves R z = e_c
+        for (int j = p - 1; j >= 0; --j) {
+            double s = (j == c) ? 1.0 : 0.0;
+            for (int l = j + 1; l < p; ++l) s -= R[(size_t)j * p + l] * Ri[(size_t)l * p + c];
+            Ri[(size_t)j * p + c] = s / R[(size_t)j * p + j];
+        }
+    }
+    const double tc = 0.5 * (double)(n + 1);
+    for (int c = 0; c < p; ++c) {
+        for (int j = 0; j < p; ++j) ops->bmap[(size_t)j * p + c] = Ri[(size_t)j * p + c];
+        ops->bmap[0 * p + c] = Ri[0 * p + c] - (tc / (double)n) * Ri[1 * p + c];
+        ops->bmap[1 * p + c] = Ri[1 * p + c] / (double)n;
+    }
+    return true;
+}
+
+}  // namespace bfm

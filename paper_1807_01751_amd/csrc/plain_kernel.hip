@@ -1,0 +1,279 @@
+// Fused plain-path kernel of BFAST Monitor for gfx950 (FP64 arithmetic).
+//
+// One lane owns one pixel and streams its series once, time-major, so every
+// wave-wide load reads 64 consecutive pixels of one time row (coalesced; the
+// paper's kernel listing in Section 3 uses the same transposed access).  The
+// steps of Algorithm 1 for that pixel run in registers, with the batched form
+// of Section 3 (one shared operator for all pixels, Eq. 7-8):
+//
+//   history rows t < n   (Eq. 5-6, Algorithm 1 steps 2-5)
+//       b' += q_t (y_t - c)      coordinates in the orthonormal history basis
+//       yy += (y_t - c)^2        so that RSS = yy - ||b'||^2
+//     c = y_0 centres the series; the intercept absorbs it exactly.
+//   monitoring rows t >= n (Eq. 3, Algorithm 1 steps 6-13)
+//       S_t = S_{t-1} + y_t - y_{t-H}   window sum of the observations; the
+//             value H rows back comes from a per-lane ring in LDS
+//       num = S_t - w_t' b'             window sum of the residuals
+//       |num| > b_t sigma sqrt(n)       boundary test of Eq. 4 (first hit)
+//       hi/lo = max/min num             MOSUM value of largest magnitude
+//
+// Neither the predictions nor the MOSUM process are materialised: Y is read
+// once and each pixel writes a break index and a magnitude.
+#include <cmath>
+
+#include "bfm_internal.hpp"
+
+namespace bfm {
+namespace {
+
+constexpr int kU = 16;  // rows per prefetch chunk
+
+template <typename T>
+__device__ __forceinline__ void put(void* base, int64_t idx, double v)
+{
+    static_cast<T*>(base)[idx] = static_cast<T>(v);
+}
+
+__device__ __forceinline__ void put_out(void* base, int64_t idx, double v, int f64)
+{
+    if (f64)
+        put<double>(base, idx, v);
+    else
+        put<float>(base, idx, v);
+}
+
+// Streams rows [t0, t1) of one pixel column, calling body(t, y_t) in order.
+// Rows are fetched in chunks of kU, one chunk ahead of the arithmetic, with two
+// register buffers used in turn.  `row` is the uniform base of row 0 and `lane`
+// the pixel's offset, so each load is a uniform 64-bit base plus a 32-bit lane
+// offset.
+template <typename Body>
+__device__ __forceinline__ void stream_rows(const float* __restrict__ Y, int64_t ld,
+                                            uint32_t lane, int t0, int t1, Body&& body)
+{
+    int t = t0;
+    if (t1 - t >= kU) {
+        float a[kU], b[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) a[u] = Y[(int64_t)(t + u) * ld + lane];
+        for (; t + 3 * kU <= t1; t += 2 * kU) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) b[u] = Y[(int64_t)(t + kU + u) * ld + lane];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) body(t + u, a[u]);
+#pragma unroll
+            for (int u = 0; u < kU; ++u) a[u] = Y[(int64_t)(t + 2 * kU + u) * ld + lane];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) body(t + kU + u, b[u]);
+        }
+        if (t + 2 * kU <= t1) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) b[u] = Y[(int64_t)(t + kU + u) * ld + lane];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) body(t + u, a[u]);
+#pragma unroll
+            for (int u = 0; u < kU; ++u) body(t + kU + u, b[u]);
+            t += 2 * kU;
+        } else {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) body(t + u, a[u]);
+            t += kU;
+        }
+    }
+    for (; t < t1; ++t) body(t, Y[(int64_t)t * ld + lane]);
+}
+
+template <int NP, bool EXPORT>
+__global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
+{
+    extern __shared__ float ring[];  // H rows x kPlainBlock lanes
+    const int tid = threadIdx.x;
+    const int64_t pix = (int64_t)blockIdx.x * kPlainBlock + tid;
+    const bool active = pix < a.P;
+    // Lanes past the end read the last pixel's column and store nothing.
+    const uint32_t lane = (uint32_t)(active ? pix : a.P - 1);
+    const int n = a.n, N = a.N, H = a.H;
+    const int64_t ld = a.ld;
+    const float* __restrict__ Y = a.Y;
+    const double* __restrict__ q = a.q;
+    const double* __restrict__ w = a.w;
+    const double* __restrict__ bnd = a.bnd;
+    float* myring = ring + tid;
+
+    const double c = (double)Y[lane];
+    double bq[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) bq[j] = 0.0;
+    double yy = 0.0, S = 0.0;
+    float ymax = 0.0f;
+
+    // History rows before the last window: fit accumulation only.
+    const int tail0 = n - H;
+    stream_rows(Y, ld, lane, 0, tail0, [&](int t, float v) {
+        const double d = (double)v - c;
+        yy = fma(d, d, yy);
+        const double* qt = q + (int64_t)t * NP;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) bq[j] = fma(qt[j], d, bq[j]);
+        ymax = fmaxf(ymax, fabsf(v));
+    });
+    // Last H history rows: also start the first window and fill the ring.
+    int slot = tail0 % H;
+    stream_rows(Y, ld, lane, tail0, n, [&](int t, float v) {
+        const double d = (double)v - c;
+        yy = fma(d, d, yy);
+        S += d;
+        const double* qt = q + (int64_t)t * NP;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) bq[j] = fma(qt[j], d, bq[j]);
+        ymax = fmaxf(ymax, fabsf(v));
+        myring[slot * kPlainBlock] = v;
+        slot = (slot + 1 == H) ? 0 : slot + 1;
+    });
+
+    // Algorithm 1, step 5, via the Gram identity in the orthonormal basis.
+    double rss = yy;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) rss = fma(-bq[j], bq[j], rss);
+    const double sig = sqrt(fmax(rss, 0.0) * a.inv_dof);
+    const double scale = sig * a.sqrt_n;
+
+    double hi = -INFINITY, lo = INFINITY;
+    int brk = -1;
+    uint64_t broken = 0;  // wave-uniform: lanes that already crossed
+    stream_rows(Y, ld, lane, n, N, [&](int t, float v) {
+        const float vo = myring[slot * kPlainBlock];
+        myring[slot * kPlainBlock] = v;
+        slot = (slot + 1 == H) ? 0 : slot + 1;
+        S += (double)v - (double)vo;
+        const int m = t - n;
+        const double* wt = w + (int64_t)m * NP;
+        double num = S;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) num = fma(-wt[j], bq[j], num);
+        const bool x = fabs(num) > bnd[m] * scale;
+        const uint64_t newly = __ballot(x) & ~broken;
+        if (newly) {
+            broken |= newly;
+            if (x && brk < 0) brk = m;
+        }
+        hi = fmax(hi, num);
+        lo = fmin(lo, num);
+        if (EXPORT && a.mosum && active)
+            put_out(a.mosum, (int64_t)m * a.P + lane, num / scale, a.out_f64);
+    });
+
+    uint8_t st = BFM_ST_OK;
+    if (!isfinite(yy) || !isfinite(S))
+        st = BFM_ST_NONFINITE;
+    else if (sig <= kSigmaRelTol * (double)ymax)
+        st = BFM_ST_DEGENERATE_SIGMA;
+    if (!active) return;
+
+    const double qnan = __builtin_nan("");
+    double mag = qnan;
+    if (st == BFM_ST_OK)
+        mag = (hi >= -lo ? hi : lo) / scale;
+    else
+        brk = -1;
+    a.brk[pix] = brk;
+    if (a.mag) put_out(a.mag, pix, mag, a.out_f64);
+    if (a.status) a.status[pix] = st;
+    if (a.sigma) put_out(a.sigma, pix, st == BFM_ST_NONFINITE ? qnan : sig, a.out_f64);
+    if (a.beta) {
+        for (int j = 0; j < NP; ++j) {
+            double v = (j == 0) ? c : 0.0;
+            for (int l = 0; l < NP; ++l) v = fma(a.bmap[j * NP + l], bq[l], v);
+            put_out(a.beta, (int64_t)j * a.P + pix, st == BFM_ST_NONFINITE ? qnan : v, a.out_f64);
+        }
+    }
+    if (EXPORT) {
+        if (a.resid) {
+            for (int t = 0; t < N; ++t) {
+                double r = qnan;
+                if (st != BFM_ST_NONFINITE) {
+                    r = (double)Y[(int64_t)t * ld + pix] - c;
+                    const double* qt = q + (int64_t)t * NP;
+                    for (int j = 0; j < NP; ++j) r = fma(-qt[j], bq[j], r);
+                }
+                put_out(a.resid, (int64_t)t * a.P + pix, r, a.out_f64);
+            }
+        }
+        if (a.mosum && st != BFM_ST_OK)
+            for (int m = 0; m < N - n; ++m) put_out(a.mosum, (int64_t)m * a.P + pix, qnan, a.out_f64);
+    }
+}
+
+// Pixels whose parameters leave nothing to fit.
+__global__ __launch_bounds__(256) void fill_status_kernel(const float* __restrict__ Y, int64_t ld,
+                                                          int64_t P, int N, int n, int p,
+                                                          uint8_t st0, bfm_outputs out,
+                                                          int mask_mode,
+                                                          const uint8_t* __restrict__ valid,
+                                                          int64_t ldv)
+{
+    const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= P) return;
+    bool bad = false;
+    if (mask_mode != BFM_MASK_NAN)
+        for (int t = 0; t < N; ++t) {
+            bool used = mask_mode == BFM_MASK_NONE || valid[(int64_t)t * ldv + pix] != 0;
+            bad |= used && !isfinite(Y[(int64_t)t * ld + pix]);
+        }
+    const uint8_t st = bad ? (uint8_t)BFM_ST_NONFINITE : st0;
+    const double qnan = __builtin_nan("");
+    const int f64 = out.out_dtype == BFM_OUT_F64;
+    out.brk[pix] = -1;
+    if (out.status) out.status[pix] = st;
+    if (out.mag) put_out(out.mag, pix, qnan, f64);
+    if (out.sigma) put_out(out.sigma, pix, qnan, f64);
+    if (out.beta)
+        for (int j = 0; j < p; ++j) put_out(out.beta, (int64_t)j * P + pix, qnan, f64);
+    if (out.resid)
+        for (int t = 0; t < N; ++t) put_out(out.resid, (int64_t)t * P + pix, qnan, f64);
+    if (out.mosum)
+        for (int m = 0; m < N - n; ++m) put_out(out.mosum, (int64_t)m * P + pix, qnan, f64);
+}
+
+template <int NP>
+hipError_t launch_np(const PlainArgs& a, hipStream_t stream)
+{
+    const dim3 grid((unsigned)((a.P + kPlainBlock - 1) / kPlainBlock));
+    const size_t lds = (size_t)a.H * kPlainBlock * sizeof(float);
+    const bool exp = a.resid || a.mosum;
+    if (exp)
+        hipLaunchKernelGGL((plain_kernel<NP, true>), grid, dim3(kPlainBlock), lds, stream, a);
+    else
+        hipLaunchKernelGGL((plain_kernel<NP, false>), grid, dim3(kPlainBlock), lds, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_plain(const PlainArgs& a, int p, hipStream_t stream)
+{
+    switch (p) {
+    case 2: return launch_np<2>(a, stream);
+    case 4: return launch_np<4>(a, stream);
+    case 6: return launch_np<6>(a, stream);
+    case 8: return launch_np<8>(a, stream);
+    case 10: return launch_np<10>(a, stream);
+    case 12: return launch_np<12>(a, stream);
+    case 14: return launch_np<14>(a, stream);
+    case 16: return launch_np<16>(a, stream);
+    case 18: return launch_np<18>(a, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fill_status(const float* Y, int64_t ld, int64_t P, int N, int n, int p,
+                              uint8_t st, const bfm_outputs& out, int mask_mode,
+                              const uint8_t* valid, int64_t ldv, hipStream_t stream)
+{
+    const dim3 grid((unsigned)((P + 255) / 256));
+    hipLaunchKernelGGL(fill_status_kernel, grid, dim3(256), 0, stream, Y, ld, P, N, n, p, st, out,
+                       mask_mode, valid, ldv);
+    return hipGetLastError();
+}
+
+}  // namespace bfm

@@ -1,0 +1,130 @@
+"""CPU tests of libbfm's host side: exported symbols, parameter validation and
+the shared operators built on the host (no GPU needed, no kernel launched)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "bfm.h")
+
+
+@pytest.fixture(scope="module")
+def bfm():
+    from paper_1807_01751_amd import bfm as b
+    if not os.path.exists(b.LIB_PATH):
+        from paper_1807_01751_amd import build
+        build.build()
+    b.load()
+    return b
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(bfm_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol(bfm):
+    decl = declared_functions()
+    assert "bfm_fit_monitor" in decl and len(decl) >= 7
+    assert sorted(bfm.EXPORTS) == decl
+    lib = ctypes.CDLL(bfm.LIB_PATH)
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert bfm.version() >= 1
+
+
+def test_params_struct_matches_header(bfm):
+    # field order and types of bfm_params / bfm_outputs as declared in the header
+    src = open(HEADER).read()
+    body = re.search(r"typedef struct \{([^{}]*)\} bfm_params;", src, re.S).group(1)
+    fields = re.findall(r"(int32_t|double)\s+(\w+);", body)
+    names = [f[0] for f in bfm.Params._fields_]
+    assert [f[1] for f in fields] == [n.rstrip("_") for n in names]
+    body = re.search(r"typedef struct \{([^{}]*)\} bfm_outputs;", src, re.S).group(1)
+    assert [f for f in re.findall(r"\*?(\w+);", body)] == [f[0] for f in bfm.Outputs._fields_]
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(N=100, n=100), -1), (dict(N=100, n=0), -1), (dict(N=100, n=50, order=9), -1),
+    (dict(N=100, n=50, order=-1), -1), (dict(N=100, n=50, freq=0.0), -1),
+    (dict(N=100, n=50, freq=float("inf")), -1), (dict(N=100, n=50, lam=0.0), -1),
+    (dict(N=100, n=50, h=0.0), -1), (dict(N=100, n=50, h=1.01), -1),
+    (dict(N=100, n=50, h_window=51), -1), (dict(N=100, n=50, h_window=-1), -1),
+    (dict(N=100, n=50, mask_mode=3), -1),
+])
+def test_check_params_rejects(bfm, kw, code):
+    prm = bfm.make_params(**kw)
+    with pytest.raises(bfm.BfmError) as e:
+        bfm.check_params(prm, 10, 10)
+    assert e.value.code == code
+
+
+def test_check_params_layout_and_accepts(bfm):
+    prm = bfm.make_params(400, 200, 3)
+    bfm.check_params(prm, 1 << 20, 1 << 20)
+    bfm.check_params(prm, 0, 0)
+    bfm.check_params(bfm.make_params(400, 200, 3, h=1.0), 5, 8)
+    bfm.check_params(bfm.make_params(400, 200, 3, h_window=200), 5, 8)
+    with pytest.raises(bfm.BfmError) as e:
+        bfm.check_params(prm, 10, 9)
+    assert e.value.code == bfm.E_LAYOUT
+    prm.precision = 7
+    with pytest.raises(bfm.BfmError):
+        bfm.check_params(prm, 10, 10)
+
+
+def test_create_without_device_reports_nodevice(bfm):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    h = ctypes.c_void_p()
+    rc = bfm.load().bfm_create(ctypes.byref(h), 0)
+    assert rc == bfm.E_NODEVICE and not h.value
+
+
+def _design(N, order, freq):
+    t = np.arange(1, N + 1, dtype=np.float64)
+    cols = [np.ones(N), t]
+    for j in range(1, order + 1):
+        cols += [np.sin(2 * np.pi * j * t / freq), np.cos(2 * np.pi * j * t / freq)]
+    return np.stack(cols, axis=1)
+
+
+@pytest.mark.parametrize("N,n,order,freq,h,hw", [(400, 200, 3, 23.0, 0.25, 0), (228, 114, 3, 23.0, 0.25, 0),
+                                                 (512, 256, 4, 23.0, 0.25, 0), (288, 144, 3, 365.0, 0.0, 72),
+                                                 (60, 30, 0, 23.0, 0.5, 0), (600, 100, 2, 12.5, 0.1, 0)])
+def test_host_operators_span_and_windows(bfm, N, n, order, freq, h, hw):
+    prm = bfm.make_params(N, n, order, freq, h if h else 0.25, hw, 2.5)
+    q, w, bnd, bmap = (x.numpy() for x in bfm.host_operators(prm))
+    p = 2 + 2 * order
+    H = hw if hw else math.floor(h * n)
+    # rows 0..n-1 are orthonormal columns
+    np.testing.assert_allclose(q[:n].T @ q[:n], np.eye(p), atol=1e-13)
+    # an exact season-trend series is reproduced at every t, history and monitor
+    X = _design(N, order, freq)
+    beta0 = np.random.default_rng(0).normal(size=p) * np.r_[1, 1e-3, np.ones(2 * order)]
+    y = X @ beta0
+    bq = q[:n].T @ y[:n]
+    np.testing.assert_allclose(q @ bq, y, atol=1e-11 * np.abs(y).max())
+    np.testing.assert_allclose(bmap @ bq, beta0, rtol=1e-9, atol=1e-12)
+    # w is the window sum of q over the H rows ending at each monitoring time
+    for m in (0, 1, N - n - 1):
+        t = n + m
+        np.testing.assert_allclose(w[m], q[t - H + 1:t + 1].sum(axis=0), atol=1e-12)
+    # boundary of Eq. 4
+    t1 = np.arange(n + 1, N + 1) / n
+    ref = 2.5 * np.sqrt(np.where(t1 <= np.e, 1.0, np.log(np.maximum(t1, 1.0))))
+    np.testing.assert_allclose(bnd, ref, rtol=1e-15)
+
+
+def test_host_operators_rank_deficient(bfm):
+    prm = bfm.make_params(60, 30, 1, freq=2.0, h=0.5)  # sin(pi t) vanishes
+    with pytest.raises(bfm.BfmError) as e:
+        bfm.host_operators(prm)
+    assert e.value.code == bfm.E_UNSUPPORTED
