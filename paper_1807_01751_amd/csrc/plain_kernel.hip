@@ -19,6 +19,7 @@
 //
 // Neither the predictions nor the MOSUM process are materialised: Y is read
 // once and each pixel writes a break index and a magnitude.
+#include <climits>
 #include <cmath>
 
 #include "bfm_internal.hpp"
@@ -27,6 +28,32 @@ namespace bfm {
 namespace {
 
 constexpr int kU = 16;  // rows per prefetch chunk
+
+// The shared operator tables never change during a launch: reading them through
+// the constant address space lets every wave fetch them with scalar loads into
+// SGPRs (one fetch per wave, no vector registers, no per-lane traffic).
+using ctab = const __attribute__((address_space(4))) double*;
+
+__device__ __forceinline__ ctab as_const(const double* p)
+{
+    return (ctab)(const __attribute__((address_space(4))) void*)(p);
+}
+
+// One observation of the lane's pixel: `row` is the wave-uniform address of a
+// time row, `lane_bytes` the pixel's byte offset inside it.  A raw buffer load
+// keeps the row base in SGPRs (a buffer resource) and the lane offset in one
+// VGPR, so stepping to the next row costs scalar adds only.
+// The series is read exactly once, so the loads carry the non-temporal hint
+// (streamed through the caches without displacing the shared tables).
+constexpr int kRsrcWord3 = 0x00020000;  // raw dword access, gfx9-family layout
+constexpr int kLoadNT = 2;              // cache-policy bits of the load: nt
+
+__device__ __forceinline__ float load_obs(const float* row, uint32_t lane_bytes)
+{
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(row), 0, -1, kRsrcWord3);
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)lane_bytes, 0, kLoadNT));
+}
 
 template <typename T>
 __device__ __forceinline__ void put(void* base, int64_t idx, double v)
@@ -44,31 +71,34 @@ __device__ __forceinline__ void put_out(void* base, int64_t idx, double v, int f
 
 // Streams rows [t0, t1) of one pixel column, calling body(t, y_t) in order.
 // Rows are fetched in chunks of kU, one chunk ahead of the arithmetic, with two
-// register buffers used in turn.  `row` is the uniform base of row 0 and `lane`
-// the pixel's offset, so each load is a uniform 64-bit base plus a 32-bit lane
-// offset.
+// register buffers used in turn.
 template <typename Body>
 __device__ __forceinline__ void stream_rows(const float* __restrict__ Y, int64_t ld,
-                                            uint32_t lane, int t0, int t1, Body&& body)
+                                            uint32_t lane_bytes, int t0, int t1, Body&& body)
 {
     int t = t0;
+    const float* row = Y + (int64_t)t * ld;
     if (t1 - t >= kU) {
         float a[kU], b[kU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) a[u] = Y[(int64_t)(t + u) * ld + lane];
+        for (int u = 0; u < kU; ++u) a[u] = load_obs(row + (int64_t)u * ld, lane_bytes);
+        row += (int64_t)kU * ld;
         for (; t + 3 * kU <= t1; t += 2 * kU) {
 #pragma unroll
-            for (int u = 0; u < kU; ++u) b[u] = Y[(int64_t)(t + kU + u) * ld + lane];
+            for (int u = 0; u < kU; ++u) b[u] = load_obs(row + (int64_t)u * ld, lane_bytes);
+            row += (int64_t)kU * ld;
 #pragma unroll
             for (int u = 0; u < kU; ++u) body(t + u, a[u]);
 #pragma unroll
-            for (int u = 0; u < kU; ++u) a[u] = Y[(int64_t)(t + 2 * kU + u) * ld + lane];
+            for (int u = 0; u < kU; ++u) a[u] = load_obs(row + (int64_t)u * ld, lane_bytes);
+            row += (int64_t)kU * ld;
 #pragma unroll
             for (int u = 0; u < kU; ++u) body(t + kU + u, b[u]);
         }
         if (t + 2 * kU <= t1) {
 #pragma unroll
-            for (int u = 0; u < kU; ++u) b[u] = Y[(int64_t)(t + kU + u) * ld + lane];
+            for (int u = 0; u < kU; ++u) b[u] = load_obs(row + (int64_t)u * ld, lane_bytes);
+            row += (int64_t)kU * ld;
 #pragma unroll
             for (int u = 0; u < kU; ++u) body(t + u, a[u]);
 #pragma unroll
@@ -80,7 +110,7 @@ __device__ __forceinline__ void stream_rows(const float* __restrict__ Y, int64_t
             t += kU;
         }
     }
-    for (; t < t1; ++t) body(t, Y[(int64_t)t * ld + lane]);
+    for (; t < t1; ++t, row += ld) body(t, load_obs(row, lane_bytes));
 }
 
 template <int NP, bool EXPORT>
@@ -92,15 +122,16 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
     const bool active = pix < a.P;
     // Lanes past the end read the last pixel's column and store nothing.
     const uint32_t lane = (uint32_t)(active ? pix : a.P - 1);
+    const uint32_t lane_bytes = lane * (uint32_t)sizeof(float);
     const int n = a.n, N = a.N, H = a.H;
     const int64_t ld = a.ld;
     const float* __restrict__ Y = a.Y;
-    const double* __restrict__ q = a.q;
-    const double* __restrict__ w = a.w;
-    const double* __restrict__ bnd = a.bnd;
+    const ctab q = as_const(a.q);
+    const ctab w = as_const(a.w);
+    const ctab bnd = as_const(a.bnd);
     float* myring = ring + tid;
 
-    const double c = (double)Y[lane];
+    const double c = (double)load_obs(Y, lane_bytes);
     double bq[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) bq[j] = 0.0;
@@ -109,21 +140,21 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
 
     // History rows before the last window: fit accumulation only.
     const int tail0 = n - H;
-    stream_rows(Y, ld, lane, 0, tail0, [&](int t, float v) {
+    stream_rows(Y, ld, lane_bytes, 0, tail0, [&](int t, float v) {
         const double d = (double)v - c;
         yy = fma(d, d, yy);
-        const double* qt = q + (int64_t)t * NP;
+        const ctab qt = q + t * NP;
 #pragma unroll
         for (int j = 0; j < NP; ++j) bq[j] = fma(qt[j], d, bq[j]);
         ymax = fmaxf(ymax, fabsf(v));
     });
     // Last H history rows: also start the first window and fill the ring.
     int slot = tail0 % H;
-    stream_rows(Y, ld, lane, tail0, n, [&](int t, float v) {
+    stream_rows(Y, ld, lane_bytes, tail0, n, [&](int t, float v) {
         const double d = (double)v - c;
         yy = fma(d, d, yy);
         S += d;
-        const double* qt = q + (int64_t)t * NP;
+        const ctab qt = q + t * NP;
 #pragma unroll
         for (int j = 0; j < NP; ++j) bq[j] = fma(qt[j], d, bq[j]);
         ymax = fmaxf(ymax, fabsf(v));
@@ -139,24 +170,20 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
     const double scale = sig * a.sqrt_n;
 
     double hi = -INFINITY, lo = INFINITY;
-    int brk = -1;
-    uint64_t broken = 0;  // wave-uniform: lanes that already crossed
-    stream_rows(Y, ld, lane, n, N, [&](int t, float v) {
+    int brk = INT_MAX;  // rows ascend, so the first crossing is the smallest m
+    stream_rows(Y, ld, lane_bytes, n, N, [&](int t, float v) {
         const float vo = myring[slot * kPlainBlock];
         myring[slot * kPlainBlock] = v;
         slot = (slot + 1 == H) ? 0 : slot + 1;
         S += (double)v - (double)vo;
         const int m = t - n;
-        const double* wt = w + (int64_t)m * NP;
+        const ctab wt = w + m * NP;
         double num = S;
 #pragma unroll
         for (int j = 0; j < NP; ++j) num = fma(-wt[j], bq[j], num);
-        const bool x = fabs(num) > bnd[m] * scale;
-        const uint64_t newly = __ballot(x) & ~broken;
-        if (newly) {
-            broken |= newly;
-            if (x && brk < 0) brk = m;
-        }
+        // Branch-free, so a whole chunk of rows stays one basic block and the
+        // independent dot products of different rows can be interleaved.
+        brk = fabs(num) > bnd[m] * scale ? min(brk, m) : brk;
         hi = fmax(hi, num);
         lo = fmin(lo, num);
         if (EXPORT && a.mosum && active)
@@ -174,8 +201,7 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
     double mag = qnan;
     if (st == BFM_ST_OK)
         mag = (hi >= -lo ? hi : lo) / scale;
-    else
-        brk = -1;
+    if (st != BFM_ST_OK || brk == INT_MAX) brk = -1;
     a.brk[pix] = brk;
     if (a.mag) put_out(a.mag, pix, mag, a.out_f64);
     if (a.status) a.status[pix] = st;
@@ -193,7 +219,7 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
                 double r = qnan;
                 if (st != BFM_ST_NONFINITE) {
                     r = (double)Y[(int64_t)t * ld + pix] - c;
-                    const double* qt = q + (int64_t)t * NP;
+                    const ctab qt = q + t * NP;
                     for (int j = 0; j < NP; ++j) r = fma(-qt[j], bq[j], r);
                 }
                 put_out(a.resid, (int64_t)t * a.P + pix, r, a.out_f64);
