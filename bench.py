@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after timing, run one 1 GiB device-to-device copy (the known-size "
+                         "reference for the HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -126,6 +129,14 @@ def main():
     p50 = lat[len(lat) // 2]
     p99 = lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]
     log(f"bench: {ms_per_step:.4f} ms/step wall, kernel mean {mean_lat:.4f} ms")
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: copy calibration: 1 GiB read + 1 GiB written")
+        del src, dst
 
     bytes_per_px = 4 * N + 4 + 4  # read FP32 y once; write int32 brk + FP32 mag
     alg_bytes = bytes_per_px * P

@@ -228,6 +228,8 @@ int bfm_fit_monitor(bfm_ctx* ctx, const bfm_params* prm, const float* Y, int64_t
     a.N = p.n_obs;
     a.n = p.n_hist;
     a.H = ops.H;
+    a.m_flat = ops.m_flat;
+    a.lambda = p.lambda;
     a.sqrt_n = std::sqrt((double)p.n_hist);
     a.inv_dof = 1.0 / (double)(p.n_hist - np);
     a.brk = out->brk;

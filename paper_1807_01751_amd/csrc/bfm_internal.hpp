@@ -23,6 +23,7 @@ constexpr int kPlainBlock = 64;              // threads per block (one wave), pl
 // equivalent).  See bfm_host_operators() in bfm.h for the meaning of each.
 struct PlainOps {
     int N = 0, n = 0, p = 0, H = 0;
+    int m_flat = 0;  // leading monitoring rows with t/n <= e (boundary = lambda)
     bool rank_ok = false;
     std::vector<double> q;     // N x p
     std::vector<double> w;     // (N-n) x p
@@ -46,6 +47,8 @@ struct PlainArgs {
     const double* bnd;   // M
     const double* bmap;  // p x p
     int N, n, H;
+    int m_flat;          // leading monitoring rows where the boundary equals lambda
+    double lambda;
     double sqrt_n;       // sqrt(n): MOSUM normaliser of Eq. 3
     double inv_dof;      // 1 / (n - p): Algorithm 1, step 5
     int32_t* brk;

@@ -61,6 +61,8 @@ bool build_plain_ops(const bfm_params& prm, PlainOps* ops)
     ops->bmap.assign((size_t)p * p, 0.0);
     for (int m = 0; m < M; ++m)
         ops->bnd[m] = prm.lambda * std::sqrt(log_plus((double)(n + 1 + m) / (double)n));
+    // log+ is exactly 1 up to t/n = e, and t/n increases with m.
+    while (ops->m_flat < M && (double)(n + 1 + ops->m_flat) / (double)n <= M_E) ++ops->m_flat;
     if (n <= p) return true;  // every pixel INSUFFICIENT; no factorisation
 
     // Householder QR of X~_n (n x p, column-major copy).

@@ -27,7 +27,10 @@
 namespace bfm {
 namespace {
 
-constexpr int kU = 16;  // rows per prefetch chunk
+#ifndef BFM_PLAIN_ROWS
+#define BFM_PLAIN_ROWS 16
+#endif
+constexpr int kU = BFM_PLAIN_ROWS;  // rows per prefetch chunk
 
 // The shared operator tables never change during a launch: reading them through
 // the constant address space lets every wave fetch them with scalar loads into
@@ -171,7 +174,8 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
 
     double hi = -INFINITY, lo = INFINITY;
     int brk = INT_MAX;  // rows ascend, so the first crossing is the smallest m
-    stream_rows(Y, ld, lane_bytes, n, N, [&](int t, float v) {
+    // One monitoring row; `thr` is the boundary b_t scaled by sigma sqrt(n).
+    auto monitor_row = [&](int t, float v, double thr) {
         const float vo = myring[slot * kPlainBlock];
         myring[slot * kPlainBlock] = v;
         slot = (slot + 1 == H) ? 0 : slot + 1;
@@ -183,12 +187,19 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
         for (int j = 0; j < NP; ++j) num = fma(-wt[j], bq[j], num);
         // Branch-free, so a whole chunk of rows stays one basic block and the
         // independent dot products of different rows can be interleaved.
-        brk = fabs(num) > bnd[m] * scale ? min(brk, m) : brk;
+        brk = fabs(num) > thr ? min(brk, m) : brk;
         hi = fmax(hi, num);
         lo = fmin(lo, num);
         if (EXPORT && a.mosum && active)
             put_out(a.mosum, (int64_t)m * a.P + lane, num / scale, a.out_f64);
-    });
+    };
+    // Eq. 4 is flat (b_t = lambda) while t/n <= e: one threshold for those rows.
+    const int t_flat = n + a.m_flat;
+    const double thr_flat = a.lambda * scale;
+    stream_rows(Y, ld, lane_bytes, n, t_flat,
+                [&](int t, float v) { monitor_row(t, v, thr_flat); });
+    stream_rows(Y, ld, lane_bytes, t_flat, N,
+                [&](int t, float v) { monitor_row(t, v, bnd[t - n] * scale); });
 
     uint8_t st = BFM_ST_OK;
     if (!isfinite(yy) || !isfinite(S))
