@@ -38,25 +38,27 @@ class _Params(ctypes.Structure):
     ]
 
 
-def build(force: bool = False) -> str:
+def build(force: bool = False, src: str = _SRC, out: str = _LIB) -> str:
     """Compile the oracle with gcc (plain -O2, no fast-math, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
+        tmp = out + ".tmp%d" % os.getpid()
         subprocess.check_call(
             ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
-             "-D_GNU_SOURCE", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+             "-D_GNU_SOURCE", "-o", tmp, src, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
-_lib = None
+class Oracle:
+    """The oracle library at ``lib_path`` (the built ``bfm_oracle.c`` by default)."""
 
+    MASK_NONE, MASK_NAN, MASK_EXPLICIT = MASK_NONE, MASK_NAN, MASK_EXPLICIT
+    OK, NONFINITE, INSUFFICIENT = OK, NONFINITE, INSUFFICIENT
+    RANK_DEFICIENT, DEGENERATE_SIGMA, NO_MONITOR = RANK_DEFICIENT, DEGENERATE_SIGMA, NO_MONITOR
 
-def _load():
-    global _lib
-    if _lib is None:
-        lib = ctypes.CDLL(build())
-        d, i64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_int32
+    def __init__(self, lib_path: str):
+        lib = ctypes.CDLL(lib_path)
+        d, i64 = ctypes.c_double, ctypes.c_int64
         vp = ctypes.c_void_p
         lib.bfo_fit_monitor.argtypes = [ctypes.POINTER(_Params), vp, i64, i64, vp, i64,
                                         vp, vp, vp, vp, vp, vp, vp, ctypes.c_int]
@@ -68,66 +70,91 @@ def _load():
         lib.bfo_boundary.restype = d
         lib.bfo_threads.argtypes = [ctypes.c_int]
         lib.bfo_threads.restype = ctypes.c_int
-        _lib = lib
-    return _lib
+        self.lib = lib
+
+    def design_row(self, t: int, order: int, freq: float) -> np.ndarray:
+        """Eq. 2: x_t for the 1-based time index t."""
+        x = np.empty(2 + 2 * order, np.float64)
+        self.lib.bfo_design_row(int(t), int(order), float(freq), _ptr(x))
+        return x
+
+    def boundary(self, lam: float, ratio: float) -> float:
+        """Eq. 4: lambda * sqrt(log+(ratio))."""
+        return self.lib.bfo_boundary(float(lam), float(ratio))
+
+    def threads(self, nthreads: int = 0) -> int:
+        return self.lib.bfo_threads(int(nthreads))
+
+    def fit_monitor(self, Y, *, n: int, order: int = 3, freq: float = 23.0, h: float = 0.25,
+                    h_window: int = 0, lam: float = 2.5, mask_mode: int = MASK_NONE,
+                    valid=None, threads: int = 1, extras: bool = True) -> dict:
+        """Run the oracle on a time-major series block ``Y`` of shape (N, P).
+
+        ``Y`` is used as float32 (the library's input type) unless it is a float64
+        array, in which case the FP64 entry point is used.
+
+        Returns a dict of numpy arrays: ``brk`` (int32, P), ``mag``, ``sigma``
+        (float64, P), ``status`` (uint8, P) and, when ``extras``, ``beta`` (p x P),
+        ``resid`` (N x P) and ``mosum`` ((N-n) x P), NaN where undefined.
+        """
+        f64 = isinstance(Y, np.ndarray) and Y.dtype == np.float64
+        Y = np.ascontiguousarray(Y, dtype=np.float64 if f64 else np.float32)
+        N, P = Y.shape
+        p = 2 + 2 * order
+        prm = _Params(N, n, order, float(freq), float(h), int(h_window), float(lam),
+                      int(mask_mode))
+        out = {
+            "brk": np.empty(P, np.int32),
+            "mag": np.empty(P, np.float64),
+            "sigma": np.empty(P, np.float64),
+            "status": np.empty(P, np.uint8),
+        }
+        if extras:
+            out["beta"] = np.empty((p, P), np.float64)
+            out["resid"] = np.empty((N, P), np.float64)
+            out["mosum"] = np.empty((N - n, P), np.float64)
+        v = None
+        if valid is not None:
+            v = np.ascontiguousarray(valid, dtype=np.uint8)
+            assert v.shape == (N, P)
+        fn = self.lib.bfo_fit_monitor_f64 if f64 else self.lib.bfo_fit_monitor
+        rc = fn(ctypes.byref(prm), _ptr(Y), P, P, _ptr(v), P,
+                _ptr(out["brk"]), _ptr(out["mag"]), _ptr(out["sigma"]), _ptr(out["status"]),
+                _ptr(out.get("beta")), _ptr(out.get("resid")), _ptr(out.get("mosum")),
+                int(threads))
+        if rc != 0:
+            raise ValueError("oracle rejected the parameters")
+        return out
 
 
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
+_default = None
+
+
+def _oracle() -> Oracle:
+    global _default
+    if _default is None:
+        _default = Oracle(build())
+    return _default
+
+
 def design_row(t: int, order: int, freq: float) -> np.ndarray:
     """Eq. 2: x_t for the 1-based time index t."""
-    x = np.empty(2 + 2 * order, np.float64)
-    _load().bfo_design_row(int(t), int(order), float(freq), _ptr(x))
-    return x
+    return _oracle().design_row(t, order, freq)
 
 
 def boundary(lam: float, ratio: float) -> float:
     """Eq. 4: lambda * sqrt(log+(ratio))."""
-    return _load().bfo_boundary(float(lam), float(ratio))
+    return _oracle().boundary(lam, ratio)
 
 
 def threads(nthreads: int = 0) -> int:
-    return _load().bfo_threads(int(nthreads))
+    return _oracle().threads(nthreads)
 
 
-def fit_monitor(Y, *, n: int, order: int = 3, freq: float = 23.0, h: float = 0.25,
-                h_window: int = 0, lam: float = 2.5, mask_mode: int = MASK_NONE,
-                valid=None, threads: int = 1, extras: bool = True) -> dict:
-    """Run the oracle on a time-major series block ``Y`` of shape (N, P).
-
-    ``Y`` is used as float32 (the library's input type) unless it is a float64
-    array, in which case the FP64 entry point is used.
-
-    Returns a dict of numpy arrays: ``brk`` (int32, P), ``mag``, ``sigma`` (float64,
-    P), ``status`` (uint8, P) and, when ``extras``, ``beta`` (p x P), ``resid``
-    (N x P) and ``mosum`` ((N-n) x P), NaN where undefined.
-    """
-    f64 = isinstance(Y, np.ndarray) and Y.dtype == np.float64
-    Y = np.ascontiguousarray(Y, dtype=np.float64 if f64 else np.float32)
-    N, P = Y.shape
-    p = 2 + 2 * order
-    prm = _Params(N, n, order, float(freq), float(h), int(h_window), float(lam), int(mask_mode))
-    out = {
-        "brk": np.empty(P, np.int32),
-        "mag": np.empty(P, np.float64),
-        "sigma": np.empty(P, np.float64),
-        "status": np.empty(P, np.uint8),
-    }
-    if extras:
-        out["beta"] = np.empty((p, P), np.float64)
-        out["resid"] = np.empty((N, P), np.float64)
-        out["mosum"] = np.empty((N - n, P), np.float64)
-    v = None
-    if valid is not None:
-        v = np.ascontiguousarray(valid, dtype=np.uint8)
-        assert v.shape == (N, P)
-    fn = _load().bfo_fit_monitor_f64 if f64 else _load().bfo_fit_monitor
-    rc = fn(
-        ctypes.byref(prm), _ptr(Y), P, P, _ptr(v), P,
-        _ptr(out["brk"]), _ptr(out["mag"]), _ptr(out["sigma"]), _ptr(out["status"]),
-        _ptr(out.get("beta")), _ptr(out.get("resid")), _ptr(out.get("mosum")), int(threads))
-    if rc != 0:
-        raise ValueError("oracle rejected the parameters")
-    return out
+def fit_monitor(Y, **kw) -> dict:
+    """Module-level form of Oracle.fit_monitor on the built oracle."""
+    return _oracle().fit_monitor(Y, **kw)

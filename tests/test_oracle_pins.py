@@ -293,14 +293,19 @@ def test_nan_equals_explicit_mask(orc):
         np.testing.assert_array_equal(a[k], b[k])
 
 
-def test_masked_compaction_brute_force(orc):
-    """Masked result = a plain fit on the valid subsequence at its original t."""
-    N, n, K, P, h, lam = 120, 60, 2, 5, 0.25, 2.5
+@pytest.mark.parametrize("N,n,K,P,h,lam", [(120, 60, 2, 5, 0.25, 2.5), (400, 100, 2, 24, 0.25, 2.0)])
+def test_masked_compaction_brute_force(orc, N, n, K, P, h, lam):
+    """Masked result = a plain fit on the valid subsequence at its original t.
+
+    The second shape has N/n = 4 > e, so the boundary's compacted position u/n_v
+    matters; small late steps make the crossing index sensitive to it."""
     y = noisy(N, P, order=K, seed=16)
     rng = np.random.default_rng(17)
     miss = rng.random((N, P)) < 0.25
     y[miss] = np.nan
     y[90:, 0] -= 0.3
+    for i in range(1, P, 2):
+        y[int(rng.integers(int(0.7 * N), N - 20)):, i] -= 0.03
     r = orc.fit_monitor(y, n=n, order=K, h=h, lam=lam, mask_mode=orc.MASK_NAN)
     X = design(orc, N, K, 23.0)
     for i in range(P):
@@ -316,7 +321,8 @@ def test_masked_compaction_brute_force(orc):
         assert abs(r["sigma"][i] - sig) < 1e-11
         np.testing.assert_allclose(r["mosum"][v[nv:] - n, i], mo, atol=1e-10)
         assert np.isnan(r["mosum"][:, i]).sum() == (N - n) - (len(v) - nv)
-        b = np.array([orc.boundary(lam, (u + 1) / nv) for u in range(nv, len(v))])
+        u1 = np.arange(nv + 1, len(v) + 1) / nv
+        b = lam * np.sqrt(np.where(u1 <= math.e, 1.0, np.log(np.maximum(u1, 1.0))))
         hit = np.nonzero(np.abs(mo) > b)[0]
         assert r["brk"][i] == (v[nv + hit[0]] - n if len(hit) else -1)
     assert r["brk"][0] >= 0
