@@ -19,9 +19,16 @@ struct bfm_ctx {
     struct Entry {
         bfm::PlainOps ops;
         double* dev = nullptr;  // q | w | bnd | bmap
+        bfm::PeriodicOps per;   // per.F == 0: the period-blocked kernel does not apply
+        double* pdev = nullptr; // rt | ri | hh | wh | bnd
     };
     using Key = std::tuple<int, int, int, int, double, double, double>;
     std::map<Key, Entry> plain;
+    struct MEntry {
+        bfm::MaskedOps ops;
+        double* dev = nullptr;  // x | g
+    };
+    std::map<Key, MEntry> masked;
 };
 
 namespace {
@@ -89,6 +96,58 @@ struct DeviceGuard {
     }
 };
 
+// Missing-value modes: per-pixel masked fit (csrc/masked_kernel.hip).
+int fit_masked(bfm_ctx* ctx, const bfm_params& p, const float* Y, int64_t P, int64_t ld,
+               const uint8_t* valid, int64_t ldv, const bfm_outputs& out, hipStream_t s)
+{
+    bfm_ctx::Key key{p.n_obs, p.n_hist, p.order, p.h_window, p.freq, p.h_frac, 0.0};
+    auto it = ctx->masked.find(key);
+    if (it == ctx->masked.end()) {
+        bfm_ctx::MEntry ent;
+        bfm::build_masked_ops(p, &ent.ops);
+        std::vector<double> host(ent.ops.x);
+        host.insert(host.end(), ent.ops.g.begin(), ent.ops.g.end());
+        hipError_t e = hipMalloc(&ent.dev, host.size() * sizeof(double));
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(masked operators)");
+        e = hipMemcpy(ent.dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(ent.dev);
+            return hip_fail(e, "hipMemcpy(masked operators)");
+        }
+        it = ctx->masked.emplace(key, std::move(ent)).first;
+    }
+    const bfm::MaskedOps& ops = it->second.ops;
+    const size_t lds = bfm::masked_lds_bytes(ops.cap);
+    if (lds > ctx->max_lds)
+        return fail(BFM_E_UNSUPPORTED, "window H=%d needs %zu B of LDS per workgroup (max %zu)",
+                    ops.Hmax, lds, ctx->max_lds);
+    bfm::MaskedArgs a{};
+    a.Y = Y;
+    a.ld = ld;
+    a.valid = valid;
+    a.ldv = ldv;
+    a.P = P;
+    a.x = it->second.dev;
+    a.g = it->second.dev + ops.x.size();
+    a.N = p.n_obs;
+    a.n = p.n_hist;
+    a.h_window = p.h_window;
+    a.cap = ops.cap;
+    a.h_frac = p.h_frac;
+    a.lambda = p.lambda;
+    a.brk = out.brk;
+    a.mag = out.mag;
+    a.sigma = out.sigma;
+    a.status = out.status;
+    a.beta = out.beta;
+    a.resid = out.resid;
+    a.mosum = out.mosum;
+    a.out_f64 = out.out_dtype == BFM_OUT_F64;
+    hipError_t e = bfm::launch_masked(a, p.order, p.mask_mode, s);
+    if (e != hipSuccess) return hip_fail(e, "masked kernel launch");
+    return BFM_SUCCESS;
+}
+
 }  // namespace
 
 extern "C" {
@@ -128,7 +187,11 @@ int bfm_destroy(bfm_ctx* ctx)
     if (!ctx) return BFM_SUCCESS;
     {
         DeviceGuard g(ctx->device);
-        for (auto& kv : ctx->plain)
+        for (auto& kv : ctx->plain) {
+            if (kv.second.dev) (void)hipFree(kv.second.dev);
+            if (kv.second.pdev) (void)hipFree(kv.second.pdev);
+        }
+        for (auto& kv : ctx->masked)
             if (kv.second.dev) (void)hipFree(kv.second.dev);
     }
     delete ctx;
@@ -166,14 +229,16 @@ int bfm_fit_monitor(bfm_ctx* ctx, const bfm_params* prm, const float* Y, int64_t
         if (!valid) return fail(BFM_E_INVAL, "valid is required with BFM_MASK_EXPLICIT");
         if (ldv < P) return fail(BFM_E_LAYOUT, "ldv must be >= P");
     }
-    if (prm->mask_mode != BFM_MASK_NONE)
-        return fail(BFM_E_UNSUPPORTED, "masked path not available in this build");
+    if (prm->mask_mode != BFM_MASK_NONE && prm->order > bfm::kMaskedMaxOrder)
+        return fail(BFM_E_UNSUPPORTED, "missing-value modes support order <= %d (got %d)",
+                    bfm::kMaskedMaxOrder, prm->order);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bfm_params& p = *prm;
     const int np = 2 + 2 * p.order;
 
     std::lock_guard<std::mutex> lock(ctx->mu);
     DeviceGuard g(ctx->device);
+    if (p.mask_mode != BFM_MASK_NONE) return fit_masked(ctx, p, Y, P, ld, valid, ldv, *out, s);
     bfm_ctx::Key key{p.n_obs, p.n_hist, p.order, p.h_window, p.freq, p.h_frac, p.lambda};
     auto it = ctx->plain.find(key);
     if (it == ctx->plain.end()) {
@@ -196,6 +261,23 @@ int bfm_fit_monitor(bfm_ctx* ctx, const bfm_params* prm, const float* Y, int64_t
             (void)hipFree(ent.dev);
             return hip_fail(e, "hipMemcpy(operators)");
         }
+        const int F = bfm::periodic_period(p, ent.ops);
+        if (F > 0) {
+            bfm::build_periodic_ops(p, ent.ops, F, &ent.per);
+            std::vector<double> ph(ent.per.rt);
+            ph.insert(ph.end(), ent.per.ri.begin(), ent.per.ri.end());
+            ph.insert(ph.end(), ent.per.hh.begin(), ent.per.hh.end());
+            ph.insert(ph.end(), ent.per.wh.begin(), ent.per.wh.end());
+            ph.insert(ph.end(), ent.ops.bnd.begin(), ent.ops.bnd.end());
+            e = hipMalloc(&ent.pdev, ph.size() * sizeof(double));
+            if (e == hipSuccess)
+                e = hipMemcpy(ent.pdev, ph.data(), ph.size() * sizeof(double), hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                (void)hipFree(ent.dev);
+                if (ent.pdev) (void)hipFree(ent.pdev);
+                return hip_fail(e, "periodic operators");
+            }
+        }
         it = ctx->plain.emplace(key, std::move(ent)).first;
     }
     const bfm::PlainOps& ops = it->second.ops;
@@ -215,6 +297,31 @@ int bfm_fit_monitor(bfm_ctx* ctx, const bfm_params* prm, const float* Y, int64_t
     if (lds > ctx->max_lds)
         return fail(BFM_E_UNSUPPORTED, "window H=%d needs %zu B of LDS per workgroup (max %zu)",
                     ops.H, lds, ctx->max_lds);
+    if (it->second.per.F > 0) {
+        bfm::PeriodicArgs a{};
+        a.Y = Y;
+        a.ld = ld;
+        a.P = P;
+        a.tab = it->second.pdev;
+        a.N = p.n_obs;
+        a.n = p.n_hist;
+        a.H = ops.H;
+        a.m_flat = ops.m_flat;
+        a.lambda = p.lambda;
+        a.sqrt_n = std::sqrt((double)p.n_hist);
+        a.inv_dof = 1.0 / (double)(p.n_hist - np);
+        a.brk = out->brk;
+        a.mag = out->mag;
+        a.sigma = out->sigma;
+        a.status = out->status;
+        a.beta = out->beta;
+        a.resid = out->resid;
+        a.mosum = out->mosum;
+        a.out_f64 = out->out_dtype == BFM_OUT_F64;
+        e = bfm::launch_periodic(a, p.order, it->second.per.F, s);
+        if (e != hipSuccess) return hip_fail(e, "periodic kernel launch");
+        return BFM_SUCCESS;
+    }
     const double* d = it->second.dev;
     const size_t nq = ops.q.size(), nw = ops.w.size(), nb = ops.bnd.size();
     bfm::PlainArgs a{};

@@ -29,7 +29,38 @@ struct PlainOps {
     std::vector<double> w;     // (N-n) x p
     std::vector<double> bnd;   // N-n
     std::vector<double> bmap;  // p x p
+    std::vector<double> R;     // p x p, row-major, upper: X~_n = Q R
 };
+
+// Operators of the period-blocked plain kernel, used when the number of
+// observations per year f is one of the integers below: the harmonic regressors
+// then repeat every f rows, so the history fit accumulates one sum per phase
+// and the window sums of fitted values are periodic in t (plus a linear trend).
+constexpr int kPeriods[] = {12, 23, 24};
+constexpr int kPeriodicMaxOrder = 4;
+struct PeriodicOps {
+    int F = 0;                // period in rows
+    std::vector<double> rt;   // p x p, row-major: R^-T (lower)
+    std::vector<double> ri;   // p x p, row-major: R^-1 (upper)
+    std::vector<double> hh;   // F x 2k: sin, cos of 2 pi j (t+1)/f at phase t mod F
+    std::vector<double> wh;   // F x 2k: their sums over the window ending at phase t mod F
+};
+// Returns the period to use for these parameters (0: not applicable).
+int periodic_period(const bfm_params& prm, const PlainOps& ops);
+void build_periodic_ops(const bfm_params& prm, const PlainOps& ops, int F, PeriodicOps* out);
+
+// Operators of the masked path (host FP64).  With x~_t the design row of
+// Eq. 2 in the centred-trend basis (1, tau_t, sin, cos, ...), tau_t = (t -
+// (n+1)/2)/n, the per-pixel Gram matrix sum_t w_t x~_t x~_t' is assembled from
+// 2 + 6k masked sums of the functions in `g` (product-to-sum identities).
+constexpr int kMaskedMaxOrder = 4;  // per-pixel Gram and Cholesky held in VGPRs
+struct MaskedOps {
+    int N = 0, n = 0, p = 0, ng = 0, Hmax = 0, cap = 0;
+    std::vector<double> x;  // N x p: x~_t
+    std::vector<double> g;  // n x ng: tau, tau^2, sin(m w t), cos(m w t) for m = 1..2k,
+                            // tau sin(j w t), tau cos(j w t) for j = 1..k
+};
+bool build_masked_ops(const bfm_params& prm, MaskedOps* ops);
 
 // Window length H for a history of `count` used observations.
 int window_length(const bfm_params& prm, int count);
@@ -62,6 +93,49 @@ struct PlainArgs {
 };
 
 hipError_t launch_plain(const PlainArgs& a, int p, hipStream_t stream);
+
+// Arguments of the period-blocked plain kernel.
+struct PeriodicArgs {
+    const float* Y;
+    int64_t ld;
+    int64_t P;
+    const double* tab;   // rt | ri | hh | wh | bnd
+    int N, n, H, m_flat;
+    double lambda, sqrt_n, inv_dof;
+    int32_t* brk;
+    void* mag;
+    void* sigma;
+    uint8_t* status;
+    void* beta;
+    void* resid;
+    void* mosum;
+    int out_f64;
+};
+hipError_t launch_periodic(const PeriodicArgs& a, int order, int F, hipStream_t stream);
+
+// Arguments of the masked kernel (by value; every pointer is device memory).
+struct MaskedArgs {
+    const float* Y;
+    int64_t ld;
+    const uint8_t* valid;  // EXPLICIT mode only
+    int64_t ldv;
+    int64_t P;
+    const double* x;       // N x p
+    const double* g;       // n x ng
+    int N, n, h_window, cap;
+    double h_frac, lambda;
+    int32_t* brk;
+    void* mag;
+    void* sigma;
+    uint8_t* status;
+    void* beta;
+    void* resid;
+    void* mosum;
+    int out_f64;
+};
+
+hipError_t launch_masked(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
+size_t masked_lds_bytes(int cap);
 
 // Every pixel gets `st` (or NONFINITE if one of its used observations is not
 // finite), brk = -1 and NaN floating outputs: used when the parameters make

@@ -1,0 +1,217 @@
+// Device helpers shared by the gfx950 kernels of libbfm: operator-table access,
+// series loads and the chunked row streamer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace bfm {
+namespace dev {
+
+// The shared operator tables never change during a launch: reading them through
+// the constant address space lets every wave fetch them with scalar loads into
+// SGPRs (one fetch per wave, no vector registers, no per-lane traffic).
+using ctab = const __attribute__((address_space(4))) double*;
+
+__device__ __forceinline__ ctab as_const(const double* p)
+{
+    return (ctab)(const __attribute__((address_space(4))) void*)(p);
+}
+
+// Raw buffer loads keep a time row's base address in SGPRs (a buffer
+// resource) and the lane's byte offset in one VGPR, so stepping to the next
+// row costs scalar adds only.  The series is read exactly once, so the loads
+// carry the non-temporal hint.
+constexpr int kRsrcWord3 = 0x00020000;  // raw access, gfx9-family descriptor layout
+constexpr int kLoadNT = 2;              // cache-policy bits of the load: nt
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* row)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(row), 0, -1, kRsrcWord3);
+}
+
+__device__ __forceinline__ float load_obs(const float* row, uint32_t lane_bytes)
+{
+    return __uint_as_float(
+        __builtin_amdgcn_raw_buffer_load_b32(row_rsrc(row), (int)lane_bytes, 0, kLoadNT));
+}
+
+__device__ __forceinline__ uint32_t load_flag(const uint8_t* row, uint32_t lane)
+{
+    return __builtin_amdgcn_raw_buffer_load_b8(row_rsrc(row), (int)lane, 0, kLoadNT);
+}
+
+template <typename T>
+__device__ __forceinline__ void put(void* base, int64_t idx, double v)
+{
+    static_cast<T*>(base)[idx] = static_cast<T>(v);
+}
+
+__device__ __forceinline__ void put_out(void* base, int64_t idx, double v, int f64)
+{
+    if (f64)
+        put<double>(base, idx, v);
+    else
+        put<float>(base, idx, v);
+}
+
+// Cursor over one pixel column of the time-major series.
+struct ObsCursor {
+    using value_type = float;
+    const float* row;  // wave-uniform address of the current time row
+    int64_t ld;
+    uint32_t lane_bytes;
+    __device__ __forceinline__ value_type load(int u) const
+    {
+        return load_obs(row + (int64_t)u * ld, lane_bytes);
+    }
+    __device__ __forceinline__ void advance(int k) { row += (int64_t)k * ld; }
+};
+
+// An observation and its caller-supplied validity flag (nonzero = observed).
+struct FlaggedObs {
+    float y;
+    uint32_t ok;
+};
+
+struct FlaggedCursor {
+    using value_type = FlaggedObs;
+    const float* row;
+    const uint8_t* vrow;
+    int64_t ld, ldv;
+    uint32_t lane;
+    __device__ __forceinline__ value_type load(int u) const
+    {
+        return {load_obs(row + (int64_t)u * ld, lane * 4u), load_flag(vrow + (int64_t)u * ldv, lane)};
+    }
+    __device__ __forceinline__ void advance(int k)
+    {
+        row += (int64_t)k * ld;
+        vrow += (int64_t)k * ldv;
+    }
+};
+
+// Streams rows [t0, t1) of one pixel column; `cur` must point at row t0.
+// Rows are fetched in chunks of U, one chunk ahead of the arithmetic, with two
+// register buffers used in turn.  Before the rows [t, t + count) of a chunk
+// are handed over, pre(t, count) runs (count is U, or 1 for the last rows);
+// then body(u, t + u, value) runs for each row, u being the row's position in
+// the chunk (a compile-time constant after unrolling).
+template <int U, typename Cursor, typename Body, typename Pre>
+__device__ __forceinline__ void stream_rows(Cursor cur, int t0, int t1, Body&& body, Pre&& pre)
+{
+    using V = typename Cursor::value_type;
+    int t = t0;
+    if (t1 - t >= U) {
+        V a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = cur.load(u);
+        cur.advance(U);
+        for (; t + 3 * U <= t1; t += 2 * U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) b[u] = cur.load(u);
+            cur.advance(U);
+            pre(t, U);
+#pragma unroll
+            for (int u = 0; u < U; ++u) body(u, t + u, a[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) a[u] = cur.load(u);
+            cur.advance(U);
+            pre(t + U, U);
+#pragma unroll
+            for (int u = 0; u < U; ++u) body(u, t + U + u, b[u]);
+        }
+        if (t + 2 * U <= t1) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) b[u] = cur.load(u);
+            cur.advance(U);
+            pre(t, U);
+#pragma unroll
+            for (int u = 0; u < U; ++u) body(u, t + u, a[u]);
+            pre(t + U, U);
+#pragma unroll
+            for (int u = 0; u < U; ++u) body(u, t + U + u, b[u]);
+            t += 2 * U;
+        } else {
+            pre(t, U);
+#pragma unroll
+            for (int u = 0; u < U; ++u) body(u, t + u, a[u]);
+            t += U;
+        }
+    }
+    for (; t < t1; ++t) {
+        const V v = cur.load(0);
+        cur.advance(1);
+        pre(t, 1);
+        body(0, t, v);
+    }
+}
+
+template <int U, typename Cursor, typename Body>
+__device__ __forceinline__ void stream_rows(Cursor cur, int t0, int t1, Body&& body)
+{
+    stream_rows<U>(cur, t0, t1, [&](int, int t, typename Cursor::value_type v) { body(t, v); },
+                   [](int, int) {});
+}
+
+// Streams rows [t0, t1) in blocks aligned to multiples of F in absolute time:
+// block tb covers rows [tb, tb + F) with tb % F == 0, and a row's position
+// u = t - tb (its phase t mod F) is a compile-time constant in the unrolled
+// body.  The first and last blocks may be partial.  `cur` must point at row t0.
+// Blocks are fetched one ahead of the arithmetic into two register buffers.
+// For each block, pre(tb, lo, hi) runs before body(u, tb + u, value) is called
+// for u in [lo, hi).
+template <int F, typename Cursor, typename Body, typename Pre>
+__device__ __forceinline__ void stream_aligned(Cursor cur, int t0, int t1, Body&& body, Pre&& pre)
+{
+    using V = typename Cursor::value_type;
+    if (t0 >= t1) return;
+    auto load_block = [&](V* buf, int lo, int hi) {
+        if (lo == 0 && hi == F) {
+#pragma unroll
+            for (int u = 0; u < F; ++u) buf[u] = cur.load(u);
+        } else {
+#pragma unroll
+            for (int u = 0; u < F; ++u)
+                if (u >= lo && u < hi) buf[u] = cur.load(u - lo);
+        }
+        cur.advance(hi - lo);
+    };
+    auto run_block = [&](V* buf, int tb, int lo, int hi) {
+        pre(tb, lo, hi);
+        if (lo == 0 && hi == F) {
+#pragma unroll
+            for (int u = 0; u < F; ++u) body(u, tb + u, buf[u]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < F; ++u)
+                if (u >= lo && u < hi) body(u, tb + u, buf[u]);
+        }
+    };
+    V a[F], b[F];
+    int tb = t0 - t0 % F;
+    int lo = t0 - tb;
+    int hi = t1 - tb < F ? t1 - tb : F;
+    load_block(a, lo, hi);
+    for (;;) {
+        int nb = tb + F;
+        int nhi = t1 - nb < F ? t1 - nb : F;
+        if (nb < t1) load_block(b, 0, nhi);
+        run_block(a, tb, lo, hi);
+        if (nb >= t1) break;
+        tb = nb;
+        hi = nhi;
+        nb = tb + F;
+        nhi = t1 - nb < F ? t1 - nb : F;
+        if (nb < t1) load_block(a, 0, nhi);
+        run_block(b, tb, 0, hi);
+        if (nb >= t1) break;
+        tb = nb;
+        lo = 0;
+        hi = nhi;
+    }
+}
+
+}  // namespace dev
+}  // namespace bfm

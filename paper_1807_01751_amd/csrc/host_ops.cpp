@@ -59,6 +59,7 @@ bool build_plain_ops(const bfm_params& prm, PlainOps* ops)
     ops->w.assign((size_t)M * p, 0.0);
     ops->bnd.assign(M, 0.0);
     ops->bmap.assign((size_t)p * p, 0.0);
+    ops->R.assign((size_t)p * p, 0.0);
     for (int m = 0; m < M; ++m)
         ops->bnd[m] = prm.lambda * std::sqrt(log_plus((double)(n + 1 + m) / (double)n));
     // log+ is exactly 1 up to t/n = e, and t/n increases with m.
@@ -99,6 +100,7 @@ bool build_plain_ops(const bfm_params& prm, PlainOps* ops)
     }
     if (!ok) return true;  // rank deficient: every pixel RANK_DEFICIENT
     ops->rank_ok = true;
+    ops->R = R;
 
     // History rows: Q = H_0 H_1 ... H_{p-1} [I_p; 0], reflectors stored in A
     // below the diagonal (v_j = A[j.., j], H_j = I - 2 v v' / v'v).
@@ -148,6 +150,91 @@ bool build_plain_ops(const bfm_params& prm, PlainOps* ops)
         for (int j = 0; j < p; ++j) ops->bmap[(size_t)j * p + c] = Ri[(size_t)j * p + c];
         ops->bmap[0 * p + c] = Ri[0 * p + c] - (tc / (double)n) * Ri[1 * p + c];
         ops->bmap[1 * p + c] = Ri[1 * p + c] / (double)n;
+    }
+    return true;
+}
+
+int periodic_period(const bfm_params& prm, const PlainOps& ops)
+{
+    if (!ops.rank_ok || ops.n <= ops.p || prm.order > kPeriodicMaxOrder) return 0;
+    for (int F : kPeriods)
+        if (prm.freq == (double)F && ops.H >= F) return F;
+    return 0;
+}
+
+void build_periodic_ops(const bfm_params& prm, const PlainOps& ops, int F, PeriodicOps* out)
+{
+    const int p = ops.p, k = prm.order, n = ops.n, H = ops.H;
+    out->F = F;
+    out->rt.assign((size_t)p * p, 0.0);
+    out->ri.assign((size_t)p * p, 0.0);
+    // R^-1 column by column (R z = e_c); R^-T is its transpose.
+    for (int c = 0; c < p; ++c) {
+        for (int j = p - 1; j >= 0; --j) {
+            double s = (j == c) ? 1.0 : 0.0;
+            for (int l = j + 1; l < p; ++l) s -= ops.R[(size_t)j * p + l] * out->ri[(size_t)l * p + c];
+            out->ri[(size_t)j * p + c] = s / ops.R[(size_t)j * p + j];
+        }
+    }
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j) out->rt[(size_t)i * p + j] = out->ri[(size_t)j * p + i];
+    // Harmonics at phase r = t mod F (0-based t, paper time t+1), exact reduction.
+    auto harm = [&](long t1, int j, bool cosine) {
+        double ang = (2.0 * M_PI / prm.freq) * std::fmod((double)j * (double)t1, prm.freq);
+        return cosine ? std::cos(ang) : std::sin(ang);
+    };
+    out->hh.assign((size_t)F * 2 * k, 0.0);
+    out->wh.assign((size_t)F * 2 * k, 0.0);
+    for (int r = 0; r < F; ++r) {
+        for (int j = 1; j <= k; ++j) {
+            out->hh[(size_t)r * 2 * k + 2 * (j - 1)] = harm(r + 1, j, false);
+            out->hh[(size_t)r * 2 * k + 2 * (j - 1) + 1] = harm(r + 1, j, true);
+            // window of H rows ending at a time t with t mod F = r (take t >= H)
+            long t = r + (long)F * ((H + F) / F);
+            double ws = 0.0, wc = 0.0;
+            for (long s = t - H + 1; s <= t; ++s) {
+                ws += harm(s + 1, j, false);
+                wc += harm(s + 1, j, true);
+            }
+            out->wh[(size_t)r * 2 * k + 2 * (j - 1)] = ws;
+            out->wh[(size_t)r * 2 * k + 2 * (j - 1) + 1] = wc;
+        }
+    }
+    (void)n;
+}
+
+bool build_masked_ops(const bfm_params& prm, MaskedOps* ops)
+{
+    const int N = prm.n_obs, n = prm.n_hist, k = prm.order, p = 2 + 2 * k;
+    const int ng = 2 + 6 * k;
+    ops->N = N;
+    ops->n = n;
+    ops->p = p;
+    ops->ng = ng;
+    ops->Hmax = window_length(prm, n);
+    // One spare slot: the slot about to be written never holds a live entry.
+    ops->cap = (ops->Hmax > 0 ? ops->Hmax : 0) + 1;
+    ops->x.assign((size_t)N * p, 0.0);
+    ops->g.assign((size_t)n * ng, 0.0);
+    std::vector<double> x(p);
+    for (int t = 1; t <= N; ++t) {
+        design_row_centred(t, n, k, prm.freq, x.data());
+        for (int j = 0; j < p; ++j) ops->x[(size_t)(t - 1) * p + j] = x[j];
+    }
+    for (int t = 1; t <= n; ++t) {
+        double* gr = &ops->g[(size_t)(t - 1) * ng];
+        const double tau = ((double)t - 0.5 * (double)(n + 1)) / (double)n;
+        gr[0] = tau;
+        gr[1] = tau * tau;
+        for (int m = 1; m <= 2 * k; ++m) {
+            double ang = (2.0 * M_PI / prm.freq) * std::fmod((double)m * (double)t, prm.freq);
+            gr[1 + m] = std::sin(ang);
+            gr[1 + 2 * k + m] = std::cos(ang);
+        }
+        for (int j = 1; j <= k; ++j) {
+            gr[1 + 4 * k + j] = tau * gr[1 + j];
+            gr[1 + 5 * k + j] = tau * gr[1 + 2 * k + j];
+        }
     }
     return true;
 }

@@ -23,98 +23,17 @@
 #include <cmath>
 
 #include "bfm_internal.hpp"
+#include "device_common.hpp"
 
 namespace bfm {
 namespace {
+
+using namespace dev;
 
 #ifndef BFM_PLAIN_ROWS
 #define BFM_PLAIN_ROWS 16
 #endif
 constexpr int kU = BFM_PLAIN_ROWS;  // rows per prefetch chunk
-
-// The shared operator tables never change during a launch: reading them through
-// the constant address space lets every wave fetch them with scalar loads into
-// SGPRs (one fetch per wave, no vector registers, no per-lane traffic).
-using ctab = const __attribute__((address_space(4))) double*;
-
-__device__ __forceinline__ ctab as_const(const double* p)
-{
-    return (ctab)(const __attribute__((address_space(4))) void*)(p);
-}
-
-// One observation of the lane's pixel: `row` is the wave-uniform address of a
-// time row, `lane_bytes` the pixel's byte offset inside it.  A raw buffer load
-// keeps the row base in SGPRs (a buffer resource) and the lane offset in one
-// VGPR, so stepping to the next row costs scalar adds only.
-// The series is read exactly once, so the loads carry the non-temporal hint
-// (streamed through the caches without displacing the shared tables).
-constexpr int kRsrcWord3 = 0x00020000;  // raw dword access, gfx9-family layout
-constexpr int kLoadNT = 2;              // cache-policy bits of the load: nt
-
-__device__ __forceinline__ float load_obs(const float* row, uint32_t lane_bytes)
-{
-    const __amdgpu_buffer_rsrc_t r =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(row), 0, -1, kRsrcWord3);
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)lane_bytes, 0, kLoadNT));
-}
-
-template <typename T>
-__device__ __forceinline__ void put(void* base, int64_t idx, double v)
-{
-    static_cast<T*>(base)[idx] = static_cast<T>(v);
-}
-
-__device__ __forceinline__ void put_out(void* base, int64_t idx, double v, int f64)
-{
-    if (f64)
-        put<double>(base, idx, v);
-    else
-        put<float>(base, idx, v);
-}
-
-// Streams rows [t0, t1) of one pixel column, calling body(t, y_t) in order.
-// Rows are fetched in chunks of kU, one chunk ahead of the arithmetic, with two
-// register buffers used in turn.
-template <typename Body>
-__device__ __forceinline__ void stream_rows(const float* __restrict__ Y, int64_t ld,
-                                            uint32_t lane_bytes, int t0, int t1, Body&& body)
-{
-    int t = t0;
-    const float* row = Y + (int64_t)t * ld;
-    if (t1 - t >= kU) {
-        float a[kU], b[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) a[u] = load_obs(row + (int64_t)u * ld, lane_bytes);
-        row += (int64_t)kU * ld;
-        for (; t + 3 * kU <= t1; t += 2 * kU) {
-#pragma unroll
-            for (int u = 0; u < kU; ++u) b[u] = load_obs(row + (int64_t)u * ld, lane_bytes);
-            row += (int64_t)kU * ld;
-#pragma unroll
-            for (int u = 0; u < kU; ++u) body(t + u, a[u]);
-#pragma unroll
-            for (int u = 0; u < kU; ++u) a[u] = load_obs(row + (int64_t)u * ld, lane_bytes);
-            row += (int64_t)kU * ld;
-#pragma unroll
-            for (int u = 0; u < kU; ++u) body(t + kU + u, b[u]);
-        }
-        if (t + 2 * kU <= t1) {
-#pragma unroll
-            for (int u = 0; u < kU; ++u) b[u] = load_obs(row + (int64_t)u * ld, lane_bytes);
-            row += (int64_t)kU * ld;
-#pragma unroll
-            for (int u = 0; u < kU; ++u) body(t + u, a[u]);
-#pragma unroll
-            for (int u = 0; u < kU; ++u) body(t + kU + u, b[u]);
-            t += 2 * kU;
-        } else {
-#pragma unroll
-            for (int u = 0; u < kU; ++u) body(t + u, a[u]);
-            t += kU;
-        }
-    }
-    for (; t < t1; ++t, row += ld) body(t, load_obs(row, lane_bytes));
-}
 
 template <int NP, bool EXPORT>
 __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
@@ -143,7 +62,7 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
 
     // History rows before the last window: fit accumulation only.
     const int tail0 = n - H;
-    stream_rows(Y, ld, lane_bytes, 0, tail0, [&](int t, float v) {
+    stream_rows<kU>(ObsCursor{Y + (int64_t)(0) * ld, ld, lane_bytes}, 0, tail0, [&](int t, float v) {
         const double d = (double)v - c;
         yy = fma(d, d, yy);
         const ctab qt = q + t * NP;
@@ -153,7 +72,7 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
     });
     // Last H history rows: also start the first window and fill the ring.
     int slot = tail0 % H;
-    stream_rows(Y, ld, lane_bytes, tail0, n, [&](int t, float v) {
+    stream_rows<kU>(ObsCursor{Y + (int64_t)(tail0) * ld, ld, lane_bytes}, tail0, n, [&](int t, float v) {
         const double d = (double)v - c;
         yy = fma(d, d, yy);
         S += d;
@@ -174,11 +93,8 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
 
     double hi = -INFINITY, lo = INFINITY;
     int brk = INT_MAX;  // rows ascend, so the first crossing is the smallest m
-    // One monitoring row; `thr` is the boundary b_t scaled by sigma sqrt(n).
-    auto monitor_row = [&](int t, float v, double thr) {
-        const float vo = myring[slot * kPlainBlock];
-        myring[slot * kPlainBlock] = v;
-        slot = (slot + 1 == H) ? 0 : slot + 1;
+    // One monitoring row; vo = y_{t-H}, `thr` the boundary b_t scaled by sigma sqrt(n).
+    auto monitor_row = [&](int t, float v, float vo, double thr) {
         S += (double)v - (double)vo;
         const int m = t - n;
         const ctab wt = w + m * NP;
@@ -196,10 +112,44 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
     // Eq. 4 is flat (b_t = lambda) while t/n <= e: one threshold for those rows.
     const int t_flat = n + a.m_flat;
     const double thr_flat = a.lambda * scale;
-    stream_rows(Y, ld, lane_bytes, n, t_flat,
-                [&](int t, float v) { monitor_row(t, v, thr_flat); });
-    stream_rows(Y, ld, lane_bytes, t_flat, N,
-                [&](int t, float v) { monitor_row(t, v, bnd[t - n] * scale); });
+    auto thr_at = [&](int t, bool flat) { return flat ? thr_flat : bnd[t - n] * scale; };
+    if (H >= kU) {
+        // Every ring value a chunk needs was written before the chunk began, so
+        // the chunk's reads are issued together ahead of its arithmetic.
+        float vo[kU];
+        int s0 = slot;
+        auto pre = [&](int, int count) {
+            s0 = slot;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                int s = s0 + u;
+                s -= s >= H ? H : 0;
+                if (u < count) vo[u] = myring[s * kPlainBlock];
+            }
+        };
+        auto row = [&](int u, int t, float v, bool flat) {
+            int s = s0 + u;
+            s -= s >= H ? H : 0;
+            myring[s * kPlainBlock] = v;
+            slot = s + 1 == H ? 0 : s + 1;
+            monitor_row(t, v, vo[u], thr_at(t, flat));
+        };
+        stream_rows<kU>(ObsCursor{Y + (int64_t)n * ld, ld, lane_bytes}, n, t_flat,
+                        [&](int u, int t, float v) { row(u, t, v, true); }, pre);
+        stream_rows<kU>(ObsCursor{Y + (int64_t)t_flat * ld, ld, lane_bytes}, t_flat, N,
+                        [&](int u, int t, float v) { row(u, t, v, false); }, pre);
+    } else {
+        auto row = [&](int t, float v, bool flat) {
+            const float vo1 = myring[slot * kPlainBlock];
+            myring[slot * kPlainBlock] = v;
+            slot = (slot + 1 == H) ? 0 : slot + 1;
+            monitor_row(t, v, vo1, thr_at(t, flat));
+        };
+        stream_rows<kU>(ObsCursor{Y + (int64_t)n * ld, ld, lane_bytes}, n, t_flat,
+                        [&](int t, float v) { row(t, v, true); });
+        stream_rows<kU>(ObsCursor{Y + (int64_t)t_flat * ld, ld, lane_bytes}, t_flat, N,
+                        [&](int t, float v) { row(t, v, false); });
+    }
 
     uint8_t st = BFM_ST_OK;
     if (!isfinite(yy) || !isfinite(S))

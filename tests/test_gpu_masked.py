@@ -1,0 +1,192 @@
+"""GPU parity of the missing-value path (masked Gram + Cholesky) against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from parity import compare, to_numpy
+
+pytestmark = pytest.mark.gpu
+
+ALL = ("brk", "mag", "sigma", "status", "beta", "resid", "mosum")
+
+
+@pytest.fixture(scope="module")
+def bfm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1807_01751_amd import bfm as b
+    b.load()
+    return b
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def masked_series(P, N, n, order=3, seed=0, miss=0.25, **kw):
+    from paper_1807_01751_amd.synth import apply_missing, make_missing, make_series, split_rate
+    Y, _ = make_series(P, N, n, max(order, 1), seed=seed, device="cuda", **kw)
+    r = split_rate(miss)
+    m = make_missing(N, P, iid=r, runs=r, seed=seed + 100, device="cuda")
+    return apply_missing(Y, m), m
+
+
+def run_both(bfm, orc, Y, *, n, order=3, freq=23.0, h=0.25, h_window=0, lam=2.5, mode=None,
+             valid=None, outputs=ALL):
+    mode = bfm.MASK_NAN if mode is None else mode
+    g = bfm.fit_monitor(Y, n=n, order=order, freq=freq, h=h, h_window=h_window, lam=lam,
+                        mask_mode=mode, valid=valid, outputs=outputs)
+    torch.cuda.synchronize()
+    o = orc.fit_monitor(Y.cpu().numpy(), n=n, order=order, freq=freq, h=h, h_window=h_window,
+                        lam=lam, mask_mode=mode,
+                        valid=None if valid is None else valid.cpu().numpy(), threads=0)
+    return to_numpy(g), o
+
+
+def masked_margins(o, used_hist, lam, pixels):
+    """Relative distance of |MO| to the boundary at each pixel's compacted positions
+    (Eq. 4 with u / n_v), minimised over the monitoring period (oracle's MO)."""
+    out = []
+    for i in pixels:
+        mo = o["mosum"][:, i]
+        fin = np.isfinite(mo)
+        nv = used_hist[i]
+        u1 = nv + np.cumsum(fin)[fin]  # 1-based compacted positions of observed values
+        x = u1 / nv
+        b = lam * np.sqrt(np.where(x <= np.e, 1.0, np.log(np.maximum(x, 1.0))))
+        out.append(np.min(np.abs(np.abs(mo[fin]) - b) / b) if fin.any() else np.inf)
+    return np.array(out)
+
+
+def check(g, o, lam, used_hist=None):
+    """Parity.  Pixels whose break index differs must be marginal: their MOSUM comes
+    within 1e-8 (relative) of the boundary at some observed monitoring position."""
+    diff = np.nonzero(g["brk"] != o["brk"])[0]
+    keep = np.ones(len(g["brk"]), bool)
+    if len(diff):
+        assert used_hist is not None, "break indices differ"
+        m = masked_margins(o, used_hist, lam, diff)
+        assert (m < 1e-8).all(), (diff, m)
+        keep[diff] = False
+    sel = lambda d: {k: v[..., keep] for k, v in d.items()}
+    rep = compare(sel(g), sel(o))
+    rep["marginal"] = int(len(diff))
+    return rep
+
+
+def hist_count(Y, n, valid=None):
+    h = Y[:n]
+    ok = torch.isfinite(h) if valid is None else valid[:n] != 0
+    return ok.sum(0).cpu().numpy()
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3, 4])
+def test_masked_parity_orders(bfm, orc, order):
+    say(f"case masked order={order} P=1000 N=228 n=114 miss=0.25")
+    Y, _ = masked_series(1000, 228, 114, order=order, seed=20 + order)
+    g, o = run_both(bfm, orc, Y, n=114, order=order)
+    rep = check(g, o, 2.5, hist_count(Y, 114))
+    say(rep)
+    assert (o["status"] == 0).mean() > 0.9
+
+
+def test_masked_config3_shape_small(bfm, orc):
+    """Config-3 parameters (N=400, n=200, k=3, h=0.25, 25% missing) on 4096 pixels."""
+    say("case masked config3-small P=4096 N=400 n=200")
+    Y, m = masked_series(4096, 400, 200, seed=31)
+    assert 0.2 < m.float().mean().item() < 0.3
+    g, o = run_both(bfm, orc, Y, n=200)
+    rep = check(g, o, 2.5, hist_count(Y, 200))
+    say(rep)
+
+
+def test_explicit_mask_matches_nan_mode(bfm, orc):
+    say("case explicit-vs-nan P=777 N=228")
+    Y, m = masked_series(777, 228, 114, seed=41)
+    a = to_numpy(bfm.fit_monitor(Y, n=114, mask_mode=bfm.MASK_NAN, outputs=ALL))
+    valid = (~m).to(torch.uint8).contiguous()
+    Yg = Y.clone()
+    Yg[m] = 123.0  # garbage the explicit mask must hide
+    b = to_numpy(bfm.fit_monitor(Yg, n=114, mask_mode=bfm.MASK_EXPLICIT, valid=valid, outputs=ALL))
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    o = orc.fit_monitor(Yg.cpu().numpy(), n=114, mask_mode=orc.MASK_EXPLICIT,
+                        valid=valid.cpu().numpy(), threads=0)
+    check(b, o, 2.5, hist_count(Yg, 114, valid))
+
+
+def test_all_observed_masked_equals_plain(bfm):
+    say("case all-observed masked vs plain P=2000 N=228")
+    from paper_1807_01751_amd.synth import make_series
+    Y, _ = make_series(2000, 228, 114, 3, seed=51, device="cuda")
+    a = to_numpy(bfm.fit_monitor(Y, n=114, outputs=ALL))
+    b = to_numpy(bfm.fit_monitor(Y, n=114, mask_mode=bfm.MASK_NAN, outputs=ALL))
+    np.testing.assert_array_equal(a["status"], b["status"])
+    ok = a["status"] == 0
+    np.testing.assert_allclose(b["sigma"][ok], a["sigma"][ok], rtol=1e-10)
+    np.testing.assert_allclose(b["mosum"][:, ok], a["mosum"][:, ok], rtol=1e-9, atol=1e-10)
+    np.testing.assert_allclose(b["beta"][:, ok], a["beta"][:, ok], rtol=1e-7, atol=1e-10)
+    assert (a["brk"] == b["brk"]).mean() > 0.999
+
+
+def test_masked_log_boundary_and_window_count(bfm, orc):
+    say("case masked N/n>e P=500 N=400 n=100 and h_window")
+    Y, _ = masked_series(500, 400, 100, seed=61, miss=0.3)
+    g, o = run_both(bfm, orc, Y, n=100, h=0.3)
+    check(g, o, 2.5, hist_count(Y, 100))
+    g, o = run_both(bfm, orc, Y, n=100, h_window=20)
+    check(g, o, 2.5, hist_count(Y, 100))
+
+
+def test_masked_degenerate_pixels(bfm, orc):
+    say("case masked degenerate P=128 N=120 n=60")
+    N, n, P = 120, 60, 128
+    Y, m = masked_series(P, N, n, seed=71, miss=0.1)
+    Y[:, 0] = float("nan")                      # nothing observed
+    Y[:57, 1] = float("nan")                    # at most 3 observed history values <= p
+    Y[n:, 2] = float("nan")                     # no monitoring value
+    t = torch.arange(1, N + 1, device="cuda", dtype=torch.float32)
+    Y[:, 3] = 0.5 + t * 2.0 ** -10              # exact trend: sigma = 0
+    Y[:, 3][m[:, 3]] = float("nan")
+    Y[:, 4] = float("nan")                      # observed only at one phase of the year
+    Y[22::23, 4] = 0.3 + 0.01 * torch.arange(len(range(22, N, 23)), device="cuda")
+    Y[5, 5] = float("inf")                      # Inf counts as missing in NaN mode
+    g, o = run_both(bfm, orc, Y, n=n, order=1)
+    np.testing.assert_array_equal(g["status"], o["status"])
+    assert g["status"][0] == 2 and g["status"][1] == 2 and g["status"][2] == 5
+    assert g["status"][3] == 4 and g["status"][4] in (2, 3) and g["status"][5] == 0
+    check(g, o, 2.5, hist_count(Y, n))
+    # explicit mask with a NaN at an observed position
+    valid = torch.ones(N, P, dtype=torch.uint8, device="cuda")
+    Y2 = Y.clone()
+    Y2[torch.isnan(Y2)] = 0.0
+    Y2[10, 7] = float("nan")
+    g, o = run_both(bfm, orc, Y2, n=n, order=1, mode=bfm.MASK_EXPLICIT, valid=valid)
+    np.testing.assert_array_equal(g["status"], o["status"])
+    assert g["status"][7] == 1
+
+
+def test_masked_order_limit(bfm):
+    Y, _ = masked_series(64, 100, 50, seed=81)
+    with pytest.raises(bfm.BfmError) as e:
+        bfm.fit_monitor(Y, n=50, order=5, mask_mode=bfm.MASK_NAN)
+    assert e.value.code == bfm.E_UNSUPPORTED
+
+
+def test_masked_config3_full_size_sampled(bfm, orc):
+    """1024x1024 pixels, N=400, n=200, k=3, 25% missing: sampled against the oracle."""
+    say("case masked config3 P=1048576 N=400 n=200")
+    P, N, n = 1 << 20, 400, 200
+    Y, m = masked_series(P, N, n, seed=3)
+    g = to_numpy(bfm.fit_monitor(Y, n=n, mask_mode=bfm.MASK_NAN,
+                                 outputs=("brk", "mag", "sigma", "status")))
+    rng = np.random.default_rng(1)
+    idx = np.unique(np.r_[np.arange(64), np.arange(P - 64, P), rng.integers(0, P, 4000)])
+    Ys = Y[:, torch.as_tensor(idx, device="cuda")].cpu().numpy()
+    gs = {k: v[idx] for k, v in g.items()}
+    o = orc.fit_monitor(Ys, n=n, mask_mode=orc.MASK_NAN, threads=0)
+    assert (o["status"] == 0).mean() > 0.95
+    rep = check(gs, o, 2.5, np.isfinite(Ys[:n]).sum(0))
+    say("masked config3 sample", rep)
