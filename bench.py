@@ -24,8 +24,14 @@ sys.path.insert(0, ROOT)
 METRIC = "Mpixel/s at N=400,k=8 (plain vs mixed-precision); p50/p99 tile latency"
 P, N, n, ORDER, H_FRAC, LAM, FREQ = 1 << 20, 400, 200, 3, 0.25, 2.5, 23.0
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1807_01751_amd", "csrc", "plain_kernel.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plain_1024x1024_N400.json")
+CSRC = os.path.join(ROOT, "paper_1807_01751_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "traffic_plain_1024x1024_N400.json")
+# The kernel bfm_fit_monitor launches for this workload (f = 23 is an integer
+# period and the window H = 50 >= 23, so the period-blocked kernel is used).
+KERNEL = "periodic_kernel<3, 23, false>"
+PROFILE_CMD = ("rocprofv3 {flags} -f csv -d <dir> -o run -- python3 bench.py --steps 10 "
+               "--warmup 2 --no-cpu-baseline --copy-calibration")
 
 
 def log(*a):
@@ -33,8 +39,13 @@ def log(*a):
 
 
 def kernel_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the library sources (a change invalidates the stored counters)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_per_launch():
@@ -73,6 +84,66 @@ def cpu_baseline(Y, seconds):
                       f"{dt:.1f} s on {threads} host threads"}
 
 
+def _csv(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_profiles(d):
+    """Turn rocprofv3 CSV output of the three passes under ``d`` (trace/, fetch/,
+    write/) into the summaries kept in profiles/."""
+    import glob
+    import re
+    P_ALG = (4 * N + 8) * P
+    shas = set()
+    for sub in ("trace", "fetch", "write"):
+        with open(os.path.join(d, sub + ".log")) as f:
+            shas |= set(re.findall(r"kernel_sha=([0-9a-f]+)", f.read()))
+    assert shas == {kernel_sha()}, f"profiles were taken on other sources: {shas}"
+    stats = [r for r in _csv(glob.glob(os.path.join(d, "trace", "*kernel_stats.csv"))[0])
+             if KERNEL in r["Name"]]
+    assert stats, "benchmark kernel missing from the trace"
+    st = stats[0]
+    per = {}
+    for counter, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        rows = _csv(glob.glob(os.path.join(d, sub, "*counter_collection.csv"))[0])
+        k = [float(r["Counter_Value"]) for r in rows if KERNEL in r["Kernel_Name"]]
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        calib = float(copies[-1]["Counter_Value"])  # the 1 GiB copy runs last
+        factor = (1 << 30) / (calib * 1024.0)       # bytes per counted byte
+        per[counter] = {"kib_per_dispatch": sum(k) / len(k), "dispatches": len(k),
+                        "copy_1GiB_kib": calib, "factor": factor}
+    hbm = sum(v["kib_per_dispatch"] * 1024.0 * v["factor"] for v in per.values())
+    avg_ns = float(st["AverageNs"])
+    traffic = {"kernel": KERNEL, "kernel_sha": kernel_sha(), "workload": "1024x1024 pixels, N=400",
+               "hbm_bytes_per_launch": round(hbm), "algorithmic_bytes_per_launch": P_ALG,
+               "traffic_over_algorithmic": hbm / P_ALG, "counters": per,
+               "commands": [PROFILE_CMD.format(flags="--pmc FETCH_SIZE"),
+                            PROFILE_CMD.format(flags="--pmc WRITE_SIZE")]}
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(traffic, f, indent=1)
+    md = os.path.join(PROFILES, "plain_periodic_k3_f23_1024x1024_N400_kernel_trace.md")
+    with open(md, "w") as f:
+        f.write(f"# rocprofv3 kernel trace: {KERNEL}, 1024x1024 pixels, N=400\n\n")
+        f.write("Command (from the repository root, on one MI355X):\n\n    "
+                + PROFILE_CMD.format(flags="--kernel-trace --stats") + "\n\n")
+        f.write("| kernel | calls | average ns | min ns | max ns |\n|---|---|---|---|---|\n")
+        f.write(f"| {st['Name']} | {st['Calls']} | {avg_ns:.0f} | {st['MinNs']} | {st['MaxNs']} |\n\n")
+        f.write(f"Algorithmic bytes per launch: {P_ALG} (4N + 8 per pixel). At the average duration "
+                f"this is {P_ALG / avg_ns:.1f} GB/s ({P_ALG / avg_ns / HBM_PEAK_GBS:.3f} of 8 TB/s).\n\n")
+        f.write(f"HBM traffic (FETCH_SIZE and WRITE_SIZE passes, each scaled by its reading "
+                f"for a 1 GiB device copy): {hbm:.0f} B per launch = "
+                f"{hbm / P_ALG:.4f} x algorithmic.\n\n| counter | KiB per dispatch | "
+                f"1 GiB copy reads (KiB) | scale |\n|---|---|---|---|\n")
+        for c, v in per.items():
+            f.write(f"| {c} | {v['kib_per_dispatch']:.1f} | {v['copy_1GiB_kib']:.1f} | "
+                    f"{v['factor']:.4f} |\n")
+    print(md)
+    print(TRAFFIC_FILE)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,10 +151,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="write profiles/ summaries from rocprofv3 output under DIR and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run one 1 GiB device-to-device copy (the known-size "
                          "reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
@@ -98,7 +174,8 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    log(f"bench: generating {P} x {N} series on {torch.cuda.get_device_name(dev)}")
+    log(f"bench: generating {P} x {N} series on {torch.cuda.get_device_name(dev)}; "
+        f"kernel_sha={kernel_sha()}")
     Y, _ = make_series(P, N, n, ORDER, freq=FREQ, seed=2, device=dev)
     out = {"brk": torch.empty(P, dtype=torch.int32, device=dev),
            "mag": torch.empty(P, dtype=torch.float32, device=dev)}
@@ -143,7 +220,7 @@ def main():
     achieved = alg_bytes / (mean_lat * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_per_launch(),
-            "kernel": "plain_kernel<8,false>", "algorithmic_bytes_per_launch": alg_bytes}
+            "kernel": KERNEL, "algorithmic_bytes_per_launch": alg_bytes}
     res = {"metric": METRIC, "value": round(P / (ms_per_step * 1e-3) / 1e6, 2), "unit": "Mpixel/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak",

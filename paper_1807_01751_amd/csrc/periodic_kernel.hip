@@ -29,8 +29,11 @@ namespace {
 using namespace dev;
 
 template <int K, int F, bool EXPORT>
+#ifndef BFM_PERIODIC_OCC
 // Three waves per SIMD: the LDS ring of a 50-row window allows twelve per CU.
-__global__ __launch_bounds__(kPlainBlock) __attribute__((amdgpu_waves_per_eu(3)))
+#define BFM_PERIODIC_OCC __attribute__((amdgpu_waves_per_eu(3)))
+#endif
+__global__ __launch_bounds__(kPlainBlock) BFM_PERIODIC_OCC
 void periodic_kernel(PeriodicArgs a)
 {
     constexpr int NP = 2 + 2 * K;
@@ -57,19 +60,27 @@ void periodic_kernel(PeriodicArgs a)
     double A[F];
 #pragma unroll
     for (int u = 0; u < F; ++u) A[u] = 0.0;
-    double yy = 0.0, T = 0.0;
-    float ymax = 0.0f;
+    double yy = 0.0;
+    // Trend sum T = sum_t (t+1) d_t, with t + 1 = F b + u + 1 for row u of block
+    // b: T = F sum_b b (block sum) + sum_u (u+1) A[u]; Wb = sum_t b d_t needs one
+    // FMA per row against the block index held in a register.
+    double Wb = 0.0, bidx = 0.0;
+    // max |y| over the history as an unsigned maximum of the magnitude bits
+    // (their order is the order of the magnitudes; NaN pixels are flagged anyway).
+    uint32_t ymax_bits = 0;
     auto hist = [&](int u, int t, float v) {
         const double d = (double)v - c;
         yy = fma(d, d, yy);
         A[u] += d;
-        T = fma((double)(t + 1), d, T);
-        ymax = fmaxf(ymax, fabsf(v));
+        Wb = fma(bidx, d, Wb);
+        ymax_bits = max(ymax_bits, __float_as_uint(v) & 0x7fffffffu);
+        (void)t;
     };
+    auto hist_pre = [&](int tb, int, int) { bidx = (double)(tb / F); };
     // Rows from a block boundary at or before n - H also go to the ring, so that
     // it holds the last H history rows when the history ends.
     const int B = ((n - H) / F) * F;
-    stream_aligned<F>(ObsCursor{Y, ld, lane_bytes}, 0, B, hist, no_pre);
+    stream_aligned<F>(ObsCursor{Y, ld, lane_bytes}, 0, B, hist, hist_pre);
     int slot = B % H;  // ring slot of the next row: t mod H
     stream_aligned<F>(
         ObsCursor{Y + (int64_t)B * ld, ld, lane_bytes}, B, n,
@@ -78,13 +89,16 @@ void periodic_kernel(PeriodicArgs a)
             myring[slot * kPlainBlock] = v;
             slot = slot + 1 == H ? 0 : slot + 1;
         },
-        no_pre);
+        hist_pre);
 
     // ---- fit: g = X~_n' d from the phase sums, b' = R^-T g ----
     double g[NP];
     double g0 = 0.0;
 #pragma unroll
     for (int u = 0; u < F; ++u) g0 += A[u];
+    double T = (double)F * Wb;
+#pragma unroll
+    for (int u = 0; u < F; ++u) T = fma((double)(u + 1), A[u], T);
     g[0] = g0;
     g[1] = (T - 0.5 * (double)(n + 1) * g0) / (double)n;
 #pragma unroll
@@ -113,6 +127,27 @@ void periodic_kernel(PeriodicArgs a)
     }
     const double sig = sqrt(fmax(rss, 0.0) * a.inv_dof);
     const double scale = sig * a.sqrt_n;
+    const double tc = 0.5 * (double)(n + 1);
+    const double qnan = __builtin_nan("");
+    const bool hist_bad = !isfinite(yy);
+    const bool degenerate = sig <= kSigmaRelTol * (double)__uint_as_float(ymax_bits);
+    // The fit's outputs are written now, so that the coefficients need not stay
+    // live through the monitoring loop; a non-finite monitoring value found later
+    // turns them into NaN.
+    auto write_fit = [&](bool bad) {
+        if (a.sigma) put_out(a.sigma, pix, bad ? qnan : sig, a.out_f64);
+        if (a.beta) {
+            // beta~ is in the centred-trend basis of the centred series; map it
+            // to the basis of Eq. 2: tau = (t - (n+1)/2)/n.
+            for (int j = 0; j < NP; ++j) {
+                double v = beta[j];
+                if (j == 0) v = beta[0] - (tc / (double)n) * beta[1] + c;
+                if (j == 1) v = beta[1] / (double)n;
+                put_out(a.beta, (int64_t)j * a.P + pix, bad ? qnan : v, a.out_f64);
+            }
+        }
+    };
+    if (active) write_fit(hist_bad);
 
     // ---- window sums of fitted values: Lc + gamma (t+1) + Pw[t mod F] ----
     double Pw[F];
@@ -123,7 +158,7 @@ void periodic_kernel(PeriodicArgs a)
         for (int j = 0; j < NH; ++j) s = fma(wh[u * NH + j], beta[2 + j], s);
         Pw[u] = s;
     }
-    const double Hd = (double)H, tc = 0.5 * (double)(n + 1);
+    const double Hd = (double)H;
     const double gamma = beta[1] * Hd / (double)n;
     const double Lc = Hd * beta[0] - beta[1] * Hd * (0.5 * (Hd - 1.0) + tc) / (double)n;
 
@@ -135,7 +170,7 @@ void periodic_kernel(PeriodicArgs a)
 
     // ---- monitoring period (Eq. 3, Eq. 4) ----
     double hi = -INFINITY, lo = INFINITY;
-    int brk = INT_MAX;
+    int brk = INT_MAX;  // rows ascend, so the first crossing is the smallest m
     float vo[F];
     int s0 = slot;
     // The window is at least F rows long, so a block's ring reads precede its
@@ -182,31 +217,17 @@ void periodic_kernel(PeriodicArgs a)
     stream_aligned<F>(ObsCursor{Y + (int64_t)tA * ld, ld, lane_bytes}, tA, N,
                       [&](int u, int t, float v) { row(u, t, v, bnd[t - n] * scale); }, pre_w);
 
-    uint8_t st = BFM_ST_OK;
-    if (!isfinite(yy) || !isfinite(Sp))
-        st = BFM_ST_NONFINITE;
-    else if (sig <= kSigmaRelTol * (double)ymax)
-        st = BFM_ST_DEGENERATE_SIGMA;
+    const bool bad = hist_bad || !isfinite(Sp);
+    const uint8_t st = bad ? BFM_ST_NONFINITE : degenerate ? BFM_ST_DEGENERATE_SIGMA : BFM_ST_OK;
     if (!active) return;
 
-    const double qnan = __builtin_nan("");
     double mag = qnan;
     if (st == BFM_ST_OK) mag = (hi >= -lo ? hi : lo) / scale;
     if (st != BFM_ST_OK || brk == INT_MAX) brk = -1;
     a.brk[pix] = brk;
     if (a.mag) put_out(a.mag, pix, mag, a.out_f64);
     if (a.status) a.status[pix] = st;
-    if (a.sigma) put_out(a.sigma, pix, st == BFM_ST_NONFINITE ? qnan : sig, a.out_f64);
-    if (a.beta) {
-        // beta~ is in the centred-trend basis of the centred series; map it to
-        // the basis of Eq. 2: tau = (t - (n+1)/2)/n.
-        for (int j = 0; j < NP; ++j) {
-            double v = beta[j];
-            if (j == 0) v = beta[0] - (tc / (double)n) * beta[1] + c;
-            if (j == 1) v = beta[1] / (double)n;
-            put_out(a.beta, (int64_t)j * a.P + pix, st == BFM_ST_NONFINITE ? qnan : v, a.out_f64);
-        }
-    }
+    if (bad && !hist_bad) write_fit(true);
     if (EXPORT) {
         if (a.resid) {
             for (int t = 0; t < N; ++t) {

@@ -90,6 +90,23 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
     for (int j = 0; j < NP; ++j) rss = fma(-bq[j], bq[j], rss);
     const double sig = sqrt(fmax(rss, 0.0) * a.inv_dof);
     const double scale = sig * a.sqrt_n;
+    const double qnan = __builtin_nan("");
+    const bool hist_bad = !isfinite(yy);
+    const bool degenerate = sig <= kSigmaRelTol * (double)ymax;
+    // The fit's outputs are written now, so that the coefficients need not stay
+    // live through the monitoring loop; a non-finite monitoring value found later
+    // turns them into NaN.
+    auto write_fit = [&](bool bad) {
+        if (a.sigma) put_out(a.sigma, pix, bad ? qnan : sig, a.out_f64);
+        if (a.beta) {
+            for (int j = 0; j < NP; ++j) {
+                double v = (j == 0) ? c : 0.0;
+                for (int l = 0; l < NP; ++l) v = fma(a.bmap[j * NP + l], bq[l], v);
+                put_out(a.beta, (int64_t)j * a.P + pix, bad ? qnan : v, a.out_f64);
+            }
+        }
+    };
+    if (active) write_fit(hist_bad);
 
     double hi = -INFINITY, lo = INFINITY;
     int brk = INT_MAX;  // rows ascend, so the first crossing is the smallest m
@@ -151,29 +168,17 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
                         [&](int t, float v) { row(t, v, false); });
     }
 
-    uint8_t st = BFM_ST_OK;
-    if (!isfinite(yy) || !isfinite(S))
-        st = BFM_ST_NONFINITE;
-    else if (sig <= kSigmaRelTol * (double)ymax)
-        st = BFM_ST_DEGENERATE_SIGMA;
+    const bool bad = hist_bad || !isfinite(S);
+    const uint8_t st = bad ? BFM_ST_NONFINITE : degenerate ? BFM_ST_DEGENERATE_SIGMA : BFM_ST_OK;
     if (!active) return;
 
-    const double qnan = __builtin_nan("");
     double mag = qnan;
-    if (st == BFM_ST_OK)
-        mag = (hi >= -lo ? hi : lo) / scale;
+    if (st == BFM_ST_OK) mag = (hi >= -lo ? hi : lo) / scale;
     if (st != BFM_ST_OK || brk == INT_MAX) brk = -1;
     a.brk[pix] = brk;
     if (a.mag) put_out(a.mag, pix, mag, a.out_f64);
     if (a.status) a.status[pix] = st;
-    if (a.sigma) put_out(a.sigma, pix, st == BFM_ST_NONFINITE ? qnan : sig, a.out_f64);
-    if (a.beta) {
-        for (int j = 0; j < NP; ++j) {
-            double v = (j == 0) ? c : 0.0;
-            for (int l = 0; l < NP; ++l) v = fma(a.bmap[j * NP + l], bq[l], v);
-            put_out(a.beta, (int64_t)j * a.P + pix, st == BFM_ST_NONFINITE ? qnan : v, a.out_f64);
-        }
-    }
+    if (bad && !hist_bad) write_fit(true);
     if (EXPORT) {
         if (a.resid) {
             for (int t = 0; t < N; ++t) {
