@@ -6,6 +6,7 @@ from there.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import glob
 import os
 import subprocess
@@ -30,16 +31,24 @@ def sources():
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    """Compiles every source (in parallel, one hipcc per file) and links libbfm.so."""
+    jobs = []
     for src in sources():
         obj = os.path.join(CSRC, "_build", os.path.basename(src) + ".o")
         os.makedirs(os.path.dirname(obj), exist_ok=True)
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [HIPCC, *FLAGS, *lang, "-c", src, "-o", obj]
+        jobs.append(([HIPCC, *FLAGS, *lang, "-c", src, "-o", obj], obj))
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+
+    workers = max(1, min(len(jobs), os.cpu_count() or 1, 8))
+    with concurrent.futures.ThreadPoolExecutor(workers) as pool:
+        for f in [pool.submit(run, cmd) for cmd, _ in jobs]:
+            f.result()
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

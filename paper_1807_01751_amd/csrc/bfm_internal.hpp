@@ -59,7 +59,17 @@ struct MaskedOps {
     std::vector<double> x;  // N x p: x~_t
     std::vector<double> g;  // n x ng: tau, tau^2, sin(m w t), cos(m w t) for m = 1..2k,
                             // tau sin(j w t), tau cos(j w t) for j = 1..k
+    // Period-blocked masked kernel (F > 0): f is one of kPeriods, so the
+    // regressors repeat every F rows and the Gram matrix follows from per-phase
+    // observation counts.  ph is F x 4k: sin, cos of 2 pi m (t+1)/f for m = 1..2k
+    // at phase t mod F (0-based t).
+    int F = 0;
+    std::vector<double> ph;
+    std::vector<double> logn;  // N + 1: ln m for m = 0..N (boundary of Eq. 4 past e)
 };
+// Largest history length the period-blocked masked kernel takes (its per-phase
+// integer counters are exact up to there).
+constexpr int kMaskedPeriodicMaxHist = 8192;
 bool build_masked_ops(const bfm_params& prm, MaskedOps* ops);
 
 // Window length H for a history of `count` used observations.
@@ -122,6 +132,9 @@ struct MaskedArgs {
     int64_t P;
     const double* x;       // N x p
     const double* g;       // n x ng
+    const double* ph;      // F x 4k (period-blocked kernel)
+    const double* logn;    // N + 1: ln m (period-blocked kernel)
+    int F;                 // 0: general kernel
     int N, n, h_window, cap;
     double h_frac, lambda;
     int32_t* brk;
@@ -135,6 +148,7 @@ struct MaskedArgs {
 };
 
 hipError_t launch_masked(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
+hipError_t launch_masked_periodic(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
 size_t masked_lds_bytes(int cap);
 
 // Every pixel gets `st` (or NONFINITE if one of its used observations is not

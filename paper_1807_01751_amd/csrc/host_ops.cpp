@@ -236,6 +236,23 @@ bool build_masked_ops(const bfm_params& prm, MaskedOps* ops)
             gr[1 + 5 * k + j] = tau * gr[1 + 2 * k + j];
         }
     }
+    ops->F = 0;
+    ops->ph.clear();
+    if (k <= kMaskedMaxOrder && n <= kMaskedPeriodicMaxHist)
+        for (int F : kPeriods)
+            if (prm.freq == (double)F) ops->F = F;
+    if (ops->F > 0) {
+        const int F = ops->F;
+        ops->ph.assign((size_t)F * 4 * k, 0.0);
+        for (int r = 0; r < F; ++r)
+            for (int m = 1; m <= 2 * k; ++m) {
+                double ang = (2.0 * M_PI / prm.freq) * std::fmod((double)m * (double)(r + 1), prm.freq);
+                ops->ph[(size_t)r * 4 * k + 2 * (m - 1)] = std::sin(ang);
+                ops->ph[(size_t)r * 4 * k + 2 * (m - 1) + 1] = std::cos(ang);
+            }
+        ops->logn.resize((size_t)N + 1);
+        for (int m = 0; m <= N; ++m) ops->logn[m] = std::log((double)m);
+    }
     return true;
 }
 

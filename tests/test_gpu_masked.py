@@ -1,4 +1,8 @@
-"""GPU parity of the missing-value path (masked Gram + Cholesky) against the oracle."""
+"""GPU parity of the missing-value path (masked Gram + Cholesky) against the oracle.
+
+Two kernels serve this path: the period-blocked one when f is 12, 23 or 24 rows
+(per-phase counts), and the general one otherwise (masked sums per row).  The
+tests run both: f = 23 and f = 22.5 take different kernels on the same data."""
 import sys
 
 import numpy as np
@@ -25,9 +29,13 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def masked_series(P, N, n, order=3, seed=0, miss=0.25, **kw):
+# f = 23 takes the period-blocked kernel, f = 22.5 the general one.
+KERNELS = pytest.mark.parametrize("freq", [23.0, 22.5], ids=["blocked", "general"])
+
+
+def masked_series(P, N, n, order=3, seed=0, miss=0.25, freq=23.0, **kw):
     from paper_1807_01751_amd.synth import apply_missing, make_missing, make_series, split_rate
-    Y, _ = make_series(P, N, n, max(order, 1), seed=seed, device="cuda", **kw)
+    Y, _ = make_series(P, N, n, max(order, 1), freq=freq, seed=seed, device="cuda", **kw)
     r = split_rate(miss)
     m = make_missing(N, P, iid=r, runs=r, seed=seed + 100, device="cuda")
     return apply_missing(Y, m), m
@@ -82,47 +90,65 @@ def hist_count(Y, n, valid=None):
     return ok.sum(0).cpu().numpy()
 
 
+@KERNELS
 @pytest.mark.parametrize("order", [0, 1, 2, 3, 4])
-def test_masked_parity_orders(bfm, orc, order):
-    say(f"case masked order={order} P=1000 N=228 n=114 miss=0.25")
-    Y, _ = masked_series(1000, 228, 114, order=order, seed=20 + order)
-    g, o = run_both(bfm, orc, Y, n=114, order=order)
+def test_masked_parity_orders(bfm, orc, order, freq):
+    say(f"case masked order={order} f={freq} P=1000 N=228 n=114 miss=0.25")
+    Y, _ = masked_series(1000, 228, 114, order=order, seed=20 + order, freq=freq)
+    g, o = run_both(bfm, orc, Y, n=114, order=order, freq=freq)
     rep = check(g, o, 2.5, hist_count(Y, 114))
     say(rep)
     assert (o["status"] == 0).mean() > 0.9
 
 
-def test_masked_config3_shape_small(bfm, orc):
-    """Config-3 parameters (N=400, n=200, k=3, h=0.25, 25% missing) on 4096 pixels."""
-    say("case masked config3-small P=4096 N=400 n=200")
-    Y, m = masked_series(4096, 400, 200, seed=31)
+@pytest.mark.parametrize("freq,order,N,n", [(12.0, 2, 150, 61), (24.0, 4, 250, 97), (12.0, 4, 300, 50),
+                                            (24.0, 1, 100, 11), (23.0, 3, 160, 90)])
+def test_masked_blocked_periods(bfm, orc, freq, order, N, n):
+    """The other periods of the blocked kernel, histories that end inside a period,
+    a history shorter than one period and N/n > e (log boundary past e)."""
+    say(f"case masked blocked f={freq} k={order} N={N} n={n} P=777")
+    Y, _ = masked_series(777, N, n, order=order, seed=int(freq) + order + n, freq=freq, miss=0.2)
+    g, o = run_both(bfm, orc, Y, n=n, order=order, freq=freq, h=0.3)
+    rep = check(g, o, 2.5, hist_count(Y, n))
+    say(rep)
+    assert (o["status"] == 0).mean() > 0.5
+
+
+@KERNELS
+def test_masked_config3_shape_small(bfm, orc, freq):
+    """N=400, n=200, k=3, h=0.25, 25% missing on 4096 pixels."""
+    say(f"case masked N=400 n=200 f={freq} P=4096")
+    Y, m = masked_series(4096, 400, 200, seed=31, freq=freq)
     assert 0.2 < m.float().mean().item() < 0.3
-    g, o = run_both(bfm, orc, Y, n=200)
+    g, o = run_both(bfm, orc, Y, n=200, freq=freq)
     rep = check(g, o, 2.5, hist_count(Y, 200))
     say(rep)
 
 
-def test_explicit_mask_matches_nan_mode(bfm, orc):
-    say("case explicit-vs-nan P=777 N=228")
-    Y, m = masked_series(777, 228, 114, seed=41)
-    a = to_numpy(bfm.fit_monitor(Y, n=114, mask_mode=bfm.MASK_NAN, outputs=ALL))
+@KERNELS
+def test_explicit_mask_matches_nan_mode(bfm, orc, freq):
+    say(f"case explicit-vs-nan f={freq} P=777 N=228")
+    Y, m = masked_series(777, 228, 114, seed=41, freq=freq)
+    a = to_numpy(bfm.fit_monitor(Y, n=114, freq=freq, mask_mode=bfm.MASK_NAN, outputs=ALL))
     valid = (~m).to(torch.uint8).contiguous()
     Yg = Y.clone()
     Yg[m] = 123.0  # garbage the explicit mask must hide
-    b = to_numpy(bfm.fit_monitor(Yg, n=114, mask_mode=bfm.MASK_EXPLICIT, valid=valid, outputs=ALL))
+    b = to_numpy(bfm.fit_monitor(Yg, n=114, freq=freq, mask_mode=bfm.MASK_EXPLICIT, valid=valid,
+                                 outputs=ALL))
     for k in a:
         np.testing.assert_array_equal(a[k], b[k], err_msg=k)
-    o = orc.fit_monitor(Yg.cpu().numpy(), n=114, mask_mode=orc.MASK_EXPLICIT,
+    o = orc.fit_monitor(Yg.cpu().numpy(), n=114, freq=freq, mask_mode=orc.MASK_EXPLICIT,
                         valid=valid.cpu().numpy(), threads=0)
     check(b, o, 2.5, hist_count(Yg, 114, valid))
 
 
-def test_all_observed_masked_equals_plain(bfm):
-    say("case all-observed masked vs plain P=2000 N=228")
+@KERNELS
+def test_all_observed_masked_equals_plain(bfm, freq):
+    say(f"case all-observed masked vs plain f={freq} P=2000 N=228")
     from paper_1807_01751_amd.synth import make_series
-    Y, _ = make_series(2000, 228, 114, 3, seed=51, device="cuda")
-    a = to_numpy(bfm.fit_monitor(Y, n=114, outputs=ALL))
-    b = to_numpy(bfm.fit_monitor(Y, n=114, mask_mode=bfm.MASK_NAN, outputs=ALL))
+    Y, _ = make_series(2000, 228, 114, 3, freq=freq, seed=51, device="cuda")
+    a = to_numpy(bfm.fit_monitor(Y, n=114, freq=freq, outputs=ALL))
+    b = to_numpy(bfm.fit_monitor(Y, n=114, freq=freq, mask_mode=bfm.MASK_NAN, outputs=ALL))
     np.testing.assert_array_equal(a["status"], b["status"])
     ok = a["status"] == 0
     np.testing.assert_allclose(b["sigma"][ok], a["sigma"][ok], rtol=1e-10)
@@ -131,19 +157,21 @@ def test_all_observed_masked_equals_plain(bfm):
     assert (a["brk"] == b["brk"]).mean() > 0.999
 
 
-def test_masked_log_boundary_and_window_count(bfm, orc):
-    say("case masked N/n>e P=500 N=400 n=100 and h_window")
-    Y, _ = masked_series(500, 400, 100, seed=61, miss=0.3)
-    g, o = run_both(bfm, orc, Y, n=100, h=0.3)
+@KERNELS
+def test_masked_log_boundary_and_window_count(bfm, orc, freq):
+    say(f"case masked N/n>e f={freq} P=500 N=400 n=100 and h_window")
+    Y, _ = masked_series(500, 400, 100, seed=61, miss=0.3, freq=freq)
+    g, o = run_both(bfm, orc, Y, n=100, h=0.3, freq=freq)
     check(g, o, 2.5, hist_count(Y, 100))
-    g, o = run_both(bfm, orc, Y, n=100, h_window=20)
+    g, o = run_both(bfm, orc, Y, n=100, h_window=20, freq=freq)
     check(g, o, 2.5, hist_count(Y, 100))
 
 
-def test_masked_degenerate_pixels(bfm, orc):
-    say("case masked degenerate P=128 N=120 n=60")
+@KERNELS
+def test_masked_degenerate_pixels(bfm, orc, freq):
+    say(f"case masked degenerate f={freq} P=128 N=120 n=60")
     N, n, P = 120, 60, 128
-    Y, m = masked_series(P, N, n, seed=71, miss=0.1)
+    Y, m = masked_series(P, N, n, seed=71, miss=0.1, freq=freq)
     Y[:, 0] = float("nan")                      # nothing observed
     Y[:57, 1] = float("nan")                    # at most 3 observed history values <= p
     Y[n:, 2] = float("nan")                     # no monitoring value
@@ -153,17 +181,19 @@ def test_masked_degenerate_pixels(bfm, orc):
     Y[:, 4] = float("nan")                      # observed only at one phase of the year
     Y[22::23, 4] = 0.3 + 0.01 * torch.arange(len(range(22, N, 23)), device="cuda")
     Y[5, 5] = float("inf")                      # Inf counts as missing in NaN mode
-    g, o = run_both(bfm, orc, Y, n=n, order=1)
+    Y[:40, 6] = float("nan")                    # first observation late in the history
+    g, o = run_both(bfm, orc, Y, n=n, order=1, freq=freq)
     np.testing.assert_array_equal(g["status"], o["status"])
     assert g["status"][0] == 2 and g["status"][1] == 2 and g["status"][2] == 5
     assert g["status"][3] == 4 and g["status"][4] in (2, 3) and g["status"][5] == 0
+    assert g["status"][6] == 0
     check(g, o, 2.5, hist_count(Y, n))
     # explicit mask with a NaN at an observed position
     valid = torch.ones(N, P, dtype=torch.uint8, device="cuda")
     Y2 = Y.clone()
     Y2[torch.isnan(Y2)] = 0.0
     Y2[10, 7] = float("nan")
-    g, o = run_both(bfm, orc, Y2, n=n, order=1, mode=bfm.MASK_EXPLICIT, valid=valid)
+    g, o = run_both(bfm, orc, Y2, n=n, order=1, mode=bfm.MASK_EXPLICIT, valid=valid, freq=freq)
     np.testing.assert_array_equal(g["status"], o["status"])
     assert g["status"][7] == 1
 
@@ -190,3 +220,16 @@ def test_masked_config3_full_size_sampled(bfm, orc):
     assert (o["status"] == 0).mean() > 0.95
     rep = check(gs, o, 2.5, np.isfinite(Ys[:n]).sum(0))
     say("masked config3 sample", rep)
+
+
+@KERNELS
+def test_masked_lean_matches_export(bfm, freq):
+    """The variant without per-row exports gives the same break, magnitude, sigma and
+    status, bit for bit."""
+    say(f"case masked lean-vs-export f={freq} P=3000 N=300 n=150")
+    Y, _ = masked_series(3000, 300, 150, seed=91, freq=freq)
+    a = to_numpy(bfm.fit_monitor(Y, n=150, freq=freq, mask_mode=bfm.MASK_NAN,
+                                 outputs=("brk", "mag", "sigma", "status")))
+    b = to_numpy(bfm.fit_monitor(Y, n=150, freq=freq, mask_mode=bfm.MASK_NAN, outputs=ALL))
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
