@@ -26,7 +26,7 @@ struct bfm_ctx {
     std::map<Key, Entry> plain;
     struct MEntry {
         bfm::MaskedOps ops;
-        double* dev = nullptr;  // x | g | ph | logn
+        double* dev = nullptr;  // x | g | ph
     };
     std::map<Key, MEntry> masked;
 };
@@ -108,7 +108,6 @@ int fit_masked(bfm_ctx* ctx, const bfm_params& p, const float* Y, int64_t P, int
         std::vector<double> host(ent.ops.x);
         host.insert(host.end(), ent.ops.g.begin(), ent.ops.g.end());
         host.insert(host.end(), ent.ops.ph.begin(), ent.ops.ph.end());
-        host.insert(host.end(), ent.ops.logn.begin(), ent.ops.logn.end());
         hipError_t e = hipMalloc(&ent.dev, host.size() * sizeof(double));
         if (e != hipSuccess) return hip_fail(e, "hipMalloc(masked operators)");
         e = hipMemcpy(ent.dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
@@ -119,7 +118,11 @@ int fit_masked(bfm_ctx* ctx, const bfm_params& p, const float* Y, int64_t P, int
         it = ctx->masked.emplace(key, std::move(ent)).first;
     }
     const bfm::MaskedOps& ops = it->second.ops;
-    const size_t lds = bfm::masked_lds_bytes(ops.cap);
+    // The period-blocked kernel addresses F rows of one block with 32-bit offsets.
+    const int64_t lim = (int64_t)1 << 31;
+    const bool blocked = ops.F > 0 && ld * 4 * ops.F < lim &&
+                         (p.mask_mode != BFM_MASK_EXPLICIT || ldv * ops.F < lim);
+    const size_t lds = blocked ? bfm::masked_periodic_lds_bytes(ops.cap) : bfm::masked_lds_bytes(ops.cap);
     if (lds > ctx->max_lds)
         return fail(BFM_E_UNSUPPORTED, "window H=%d needs %zu B of LDS per workgroup (max %zu)",
                     ops.Hmax, lds, ctx->max_lds);
@@ -132,7 +135,6 @@ int fit_masked(bfm_ctx* ctx, const bfm_params& p, const float* Y, int64_t P, int
     a.x = it->second.dev;
     a.g = it->second.dev + ops.x.size();
     a.ph = a.g + ops.g.size();
-    a.logn = a.ph + ops.ph.size();
     a.F = ops.F;
     a.N = p.n_obs;
     a.n = p.n_hist;
@@ -148,10 +150,6 @@ int fit_masked(bfm_ctx* ctx, const bfm_params& p, const float* Y, int64_t P, int
     a.resid = out.resid;
     a.mosum = out.mosum;
     a.out_f64 = out.out_dtype == BFM_OUT_F64;
-    // The period-blocked kernel addresses F rows of one block with 32-bit offsets.
-    const int64_t lim = (int64_t)1 << 31;
-    const bool blocked = ops.F > 0 && ld * 4 * ops.F < lim &&
-                         (p.mask_mode != BFM_MASK_EXPLICIT || ldv * ops.F < lim);
     hipError_t e = blocked ? bfm::launch_masked_periodic(a, p.order, p.mask_mode, s)
                            : bfm::launch_masked(a, p.order, p.mask_mode, s);
     if (e != hipSuccess) return hip_fail(e, "masked kernel launch");

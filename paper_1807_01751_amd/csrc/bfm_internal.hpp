@@ -65,10 +65,10 @@ struct MaskedOps {
     // at phase t mod F (0-based t).
     int F = 0;
     std::vector<double> ph;
-    std::vector<double> logn;  // N + 1: ln m for m = 0..N (boundary of Eq. 4 past e)
 };
 // Largest history length the period-blocked masked kernel takes (its per-phase
-// integer counters are exact up to there).
+// integer counters are exact up to there, and a history row index fits the
+// 16-bit field of its window ring).
 constexpr int kMaskedPeriodicMaxHist = 8192;
 bool build_masked_ops(const bfm_params& prm, MaskedOps* ops);
 
@@ -133,7 +133,6 @@ struct MaskedArgs {
     const double* x;       // N x p
     const double* g;       // n x ng
     const double* ph;      // F x 4k (period-blocked kernel)
-    const double* logn;    // N + 1: ln m (period-blocked kernel)
     int F;                 // 0: general kernel
     int N, n, h_window, cap;
     double h_frac, lambda;
@@ -149,6 +148,7 @@ struct MaskedArgs {
 
 hipError_t launch_masked(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
 hipError_t launch_masked_periodic(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
+size_t masked_periodic_lds_bytes(int cap);
 size_t masked_lds_bytes(int cap);
 
 // Every pixel gets `st` (or NONFINITE if one of its used observations is not

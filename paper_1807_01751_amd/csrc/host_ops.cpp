@@ -250,8 +250,6 @@ bool build_masked_ops(const bfm_params& prm, MaskedOps* ops)
                 ops->ph[(size_t)r * 4 * k + 2 * (m - 1)] = std::sin(ang);
                 ops->ph[(size_t)r * 4 * k + 2 * (m - 1) + 1] = std::cos(ang);
             }
-        ops->logn.resize((size_t)N + 1);
-        for (int m = 0; m <= N; ++m) ops->logn[m] = std::log((double)m);
     }
     return true;
 }

@@ -45,46 +45,103 @@ constexpr int kBlock = 64;           // one wave per workgroup
 constexpr uint32_t kCountBits = 12;  // acc_r = W_r + (Q_r << 12)
 constexpr uint32_t kCountMask = (1u << kCountBits) - 1;
 
+// max and min of a running extreme and a value that is either a number or the
+// quiet NaN 0x7ff8...: in IEEE mode the hardware returns the other operand for a
+// quiet NaN, so the compiler's quieting of the operands is not needed.
+__device__ __forceinline__ double max_num(double a, double b)
+{
+    double r;
+    asm volatile("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double min_num(double a, double b)
+{
+    double r;
+    asm volatile("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// Boundary test of Eq. 4 past e for one lane: |S| > lambda scale sqrt(ln(u/n_v)),
+// squared: S^2 > thr2 ln(u/n_v).  Called only for rows where some lane of the
+// wave may be past e; cross_flat (|S| > lambda scale) is necessary for a
+// crossing.  The hardware log2 in FP32 decides every case whose margin exceeds
+// 1e-5 (its error is below 1e-6 of ln(u/n_v) >= 1); the rest take the FP64
+// logarithm.
+__device__ __noinline__ bool cross_past_e(bool cross_flat, double S, double thr2, int u, int ue, int nv,
+                                          float l2nv)
+{
+    if (!cross_flat || u <= ue) return cross_flat;
+    const double s2 = S * S;
+    const double tl = thr2 * (double)((__log2f((float)u) - l2nv) * 0.69314718f);
+    if (s2 > tl * (1.0 + 1e-5)) return true;
+    if (!(s2 > tl * (1.0 - 1e-5))) return false;
+    return s2 > thr2 * log((double)u / (double)nv);
+}
+
+// A residual in a 6-byte ring slot: the low 16 of its 52 mantissa bits are
+// cleared (relative change below 2^-36) and the value stored is the value
+// returned, the one the MOSUM adds.
+__device__ __forceinline__ double ring_store(uint32_t* hi, uint16_t* mid, int slot, double r)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(r) & ~(uint64_t)0xffff;
+    hi[slot * kBlock] = (uint32_t)(b >> 32);
+    mid[slot * kBlock] = (uint16_t)(b >> 16);
+    return __longlong_as_double((long long)b);
+}
+__device__ __forceinline__ double ring_value(uint32_t hi, uint16_t mid)
+{
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | ((uint64_t)mid << 16)));
+}
+
 __device__ __forceinline__ bool observed(float v) { return isfinite(v); }
 __device__ __forceinline__ bool observed(FlaggedObs o) { return o.ok != 0; }
 __device__ __forceinline__ float value(float v) { return v; }
 __device__ __forceinline__ float value(FlaggedObs o) { return o.y; }
 
-// Streams rows [t0, t1) in blocks of F rows aligned to multiples of F, one
-// block ahead of the arithmetic in two register buffers used in turn.  Every
-// block runs the same unrolled code: a row of the block outside [t0, t1) is
-// passed with in = false (a masked-path body treats it as missing), and its load
-// reads row t1 - 1 instead.  pre(tb) runs before the rows of block tb.
-template <int F, typename At, typename Body, typename Pre>
-__device__ __forceinline__ void stream_blocks(At at, int t0, int t1, Body&& body, Pre&& pre)
+// Streams rows [t0, t1) in blocks of F rows aligned to multiples of F, two
+// blocks ahead of the arithmetic in three register buffers used in turn (the
+// loads of a wave must cover the memory latency: the LDS ring limits how many
+// waves share a compute unit).  Every block runs the same unrolled code: a row
+// of the block outside [t0, t1) is passed with in = false (a masked-path body
+// treats it as missing), and its load reads the nearest row inside instead.
+// init(buf) sees the first block before any row of it runs; pre(tb) runs before
+// the rows of block tb.
+template <int F, typename At, typename Body, typename Pre, typename Init>
+__device__ __forceinline__ void stream_blocks(At at, int t0, int t1, Body&& body, Pre&& pre, Init&& init)
 {
     using V = typename decltype(at(0))::value_type;
     if (t0 >= t1) return;
     auto load = [&](V* buf, int tb) {
         const auto cur = at(tb);
-        const int lim = t1 - 1 - tb;
+        const int first = t0 - tb, last = t1 - 1 - tb;
 #pragma unroll
-        for (int u = 0; u < F; ++u) buf[u] = cur.load(u < lim ? u : lim);
+        for (int u = 0; u < F; ++u) buf[u] = cur.load(u < first ? first : (u < last ? u : last));
     };
     auto run = [&](V* buf, int tb) {
         pre(tb);
+        const int lo = t0 - tb > 0 ? t0 - tb : 0, hi = t1 - tb < F ? t1 - tb : F;
+        const uint32_t in = ((1u << hi) - 1u) & ~((1u << lo) - 1u);  // rows of the block in range
 #pragma unroll
-        for (int u = 0; u < F; ++u) body(u, tb + u, buf[u], tb + u >= t0 && tb + u < t1);
+        for (int u = 0; u < F; ++u) body(u, tb + u, buf[u], ((in >> u) & 1u) != 0);
     };
-    V a[F], b[F];
+    V a[F], b[F], c[F];
     int tb = t0 - t0 % F;
     load(a, tb);
+    if (tb + F < t1) load(b, tb + F);
+    init(static_cast<const V*>(a));
     for (;;) {
-        int nb = tb + F;
-        if (nb < t1) load(b, nb);
+        if (tb + 2 * F < t1) load(c, tb + 2 * F);
         run(a, tb);
-        if (nb >= t1) break;
-        tb = nb;
-        nb = tb + F;
-        if (nb < t1) load(a, nb);
+        tb += F;
+        if (tb >= t1) break;
+        if (tb + 2 * F < t1) load(a, tb + 2 * F);
         run(b, tb);
-        if (nb >= t1) break;
-        tb = nb;
+        tb += F;
+        if (tb >= t1) break;
+        if (tb + 2 * F < t1) load(b, tb + 2 * F);
+        run(c, tb);
+        tb += F;
+        if (tb >= t1) break;
     }
 }
 
@@ -144,40 +201,20 @@ masked_periodic_kernel(MaskedArgs a)
     using V = typename Cur::type::value_type;
     constexpr int NP = Gk::NP, NG = Gk::NG, NL = Gk::NL;
     constexpr int NT = 4 * K;  // phase-table row: sin, cos of m w (t+1), m = 1..2k
-    extern __shared__ double ring[];  // cap slots x kBlock lanes
+    // Window ring, cap slots x kBlock lanes of 6 bytes: a 32-bit high word and a
+    // 16-bit middle word.  History slots hold (y_t as float bits, t); monitoring
+    // slots hold a residual kept to 36 mantissa bits (the low 16 bits cleared
+    // before it enters the MOSUM, so it leaves the sum exactly as it entered).
+    extern __shared__ uint32_t ring_hi[];
     const int tid = threadIdx.x;
     const int64_t pix = (int64_t)blockIdx.x * kBlock + tid;
     const bool active = pix < a.P;
     const uint32_t lane = (uint32_t)(active ? pix : a.P - 1);
     const int n = a.n, N = a.N, cap = a.cap;
     const ctab ph = as_const(a.ph);
-    double* const myring = ring + tid;
+    uint32_t* const rhi = ring_hi + tid;
+    uint16_t* const rmid = reinterpret_cast<uint16_t*>(ring_hi + cap * kBlock) + tid;
     const double c0 = 0.5 * (double)(n - 1);  // tau_t = (t - c0) / n for 0-based t
-
-    // ---- centring constant: the first observed history value ----
-    float cf = 0.0f;
-    {
-        bool have = false;
-        for (int t0 = 0; t0 < n; t0 += F) {
-            const typename Cur::type cc = Cur::at(a, t0, lane);
-            const int lim = n - 1 - t0;  // rows past the history are not read
-            V buf[F];
-#pragma unroll
-            for (int u = 0; u < F; ++u) buf[u] = cc.load(u < lim ? u : lim);
-            float first = 0.0f;
-            bool any = false;
-#pragma unroll
-            for (int u = F - 1; u >= 0; --u) {
-                const bool ok = u <= lim && observed(buf[u]);
-                first = ok ? value(buf[u]) : first;
-                any = any || ok;
-            }
-            cf = have ? cf : first;
-            have = have || any;
-            if (__all(have)) break;
-        }
-    }
-    const double c = (double)cf;
 
     // ---- history rows: per-phase counts and sums ----
     uint32_t acc[F];
@@ -193,23 +230,55 @@ masked_periodic_kernel(MaskedArgs a)
     int wp = 0;  // next ring slot; the ring has one slot more than the longest window
     uint32_t inc = 1u;
     double bd = 0.0;
+    // Centring constant c: the first observed history value, found in the first
+    // block as it arrives; only a wave with a lane that has nothing observed
+    // there scans further blocks.
+    float cf = 0.0f;
+    double c = 0.0;
+    auto first_observed = [&](const V* buf, int t0, bool have) {
+        const int lim = n - 1 - t0;
+        float first = 0.0f;
+        bool any = false;
+#pragma unroll
+        for (int u = F - 1; u >= 0; --u) {
+            const bool ok = u <= lim && observed(buf[u]);
+            first = ok ? value(buf[u]) : first;
+            any = any || ok;
+        }
+        cf = have ? cf : first;
+        return have || any;
+    };
+    auto init = [&](const V* buf) {
+        bool have = first_observed(buf, 0, false);
+        for (int t0 = F; t0 < n && !__all(have); t0 += F) {
+            const typename Cur::type cc = Cur::at(a, t0, lane);
+            const int lim = n - 1 - t0;
+            V more[F];
+#pragma unroll
+            for (int u = 0; u < F; ++u) more[u] = cc.load(u < lim ? u : lim);
+            have = first_observed(more, t0, have);
+        }
+        c = (double)cf;
+    };
     stream_blocks<F>(
         [&](int t) { return Cur::at(a, t, lane); }, 0, n,
         [&](int u, int t, V val, bool in) {
             const bool ok = in && observed(val);
             const float v = value(val);
             if (EXPLICIT) bad = bad || (ok && !isfinite(v));
-            const float vs = ok ? v : cf;  // a missing row adds exactly zero below
-            const double d = (double)vs - c;
-            A[u] += d;
-            yy = fma(d, d, yy);
-            Bd = fma(bd, d, Bd);
-            acc[u] += ok ? inc : 0u;
-            cnt += ok ? 1u : 0u;
-            ymaxb = max(ymaxb, __float_as_uint(vs) & 0x7fffffffu);
-            myring[wp * kBlock] = __hiloint2double(t, __float_as_int(vs));
-            wp += ok ? 1 : 0;
-            wp = wp == cap ? 0 : wp;
+            // Lanes whose row is missing sit this one out (execution mask, no selects).
+            if (ok) {
+                const double d = (double)v - c;
+                A[u] += d;
+                yy = fma(d, d, yy);
+                Bd = fma(bd, d, Bd);
+                acc[u] += inc;
+                ++cnt;
+                ymaxb = max(ymaxb, __float_as_uint(v) & 0x7fffffffu);
+                rhi[wp * kBlock] = __float_as_uint(v);
+                rmid[wp * kBlock] = (uint16_t)t;
+                wp = wp + 1 == cap ? 0 : wp + 1;
+            }
         },
         [&](int tb) {
             const uint32_t b = (uint32_t)(tb / F);
@@ -218,7 +287,8 @@ masked_periodic_kernel(MaskedArgs a)
             if (b > 0) zs += (2u * b - 1u) * cnt;
             inc = 1u + (b << kCountBits);
             bd = (double)b;
-        });
+        },
+        init);
 
     // ---- Gram matrix and right-hand side from the phase sums (Eq. 5-6) ----
     const int nv = (int)cnt;
@@ -337,8 +407,8 @@ masked_periodic_kernel(MaskedArgs a)
         int slot = wp - H + i;
         slot += slot < 0 ? cap : 0;
         if (monitor && i < H) {
-            const double e = myring[slot * kBlock];
-            const int t = __double2hiint(e);
+            const float y = __uint_as_float(rhi[slot * kBlock]);
+            const int t = rmid[slot * kBlock];
             const int r = t % F;
             double pr = fma(beta[1], ((double)t - c0) * inv_n, beta[0] + c);
             const double* hr = a.ph + r * NT;
@@ -347,8 +417,7 @@ masked_periodic_kernel(MaskedArgs a)
                 pr = fma(beta[2 * j], hr[2 * (j - 1)], pr);
                 pr = fma(beta[2 * j + 1], hr[2 * (j - 1) + 1], pr);
             }
-            const double res = (double)__int_as_float(__double2loint(e)) - pr;
-            myring[slot * kBlock] = res;
+            const double res = ring_store(rhi, rmid, slot, (double)y - pr);
             S += res;
         }
     }
@@ -358,7 +427,7 @@ masked_periodic_kernel(MaskedArgs a)
     rp += rp < 0 ? cap : 0;
     const double thr_flat = a.lambda * scale;
     const double thr2 = thr_flat * thr_flat;
-    const double lnv = a.logn[nv];
+    const float l2nv = __log2f((float)nv);
     // Largest compacted count m with m / n_v <= e: up to there log+ is 1.
     int ue = (int)floor(M_E * (double)nv);
     while (ue > 0 && (double)ue / (double)nv > M_E) --ue;
@@ -376,38 +445,37 @@ masked_periodic_kernel(MaskedArgs a)
     double Gb = 0.0;
     const double rscale = 1.0 / scale;
     auto pre = [&](int tb) { Gb = gamma * (double)(tb / F); };
+    // The residual leaving the window is read one observation ahead (after the
+    // previous write, so the window still holds exactly the last H residuals):
+    // its LDS latency overlaps the rest of the row.
+    uint32_t old_hi = rhi[rp * kBlock];
+    uint16_t old_mid = rmid[rp * kBlock];
     stream_blocks<F>(
         [&](int t) { return Cur::at(a, t, lane); }, n, N,
         [&](int u, int t, V val, bool in) {
             const bool ok = in && observed(val);
             const float v = value(val);
             if (EXPLICIT) bad = bad || (ok && !isfinite(v));
-            const float vs = ok ? v : cf;
-            const double r = (double)vs - (Pw[u] + Gb);
-            const double old = myring[rp * kBlock];
-            myring[wp * kBlock] = r;
-            const double Sn = S + (r - old);
-            S = ok ? Sn : S;
-            const double Sm = ok ? Sn : qnan;  // NaN on missing rows: max, min and > skip it
-            hi = fmax(hi, Sm);
-            lo = fmin(lo, Sm);
-            wp += ok ? 1 : 0;
-            wp = wp == cap ? 0 : wp;
-            rp += ok ? 1 : 0;
-            rp = rp == cap ? 0 : rp;
-            u1 += ok ? 1 : 0;
-            bool cross = fabs(Sm) > thr_flat;
-            if (t >= t_split) {  // wave-uniform; not reached while every u/n_v stays below e
-                // Eq. 4 past e: |S| > lambda scale sqrt(ln u - ln n_v), squared.
-                const double lg = a.logn[u1] - lnv;
-                cross = Sm * Sm > (u1 > ue ? thr2 * lg : thr2);
+            if (ok) {  // lanes whose row is missing sit this one out
+                const double r = ring_store(rhi, rmid, wp, (double)v - (Pw[u] + Gb));
+                S += r - ring_value(old_hi, old_mid);
+                wp = wp + 1 == cap ? 0 : wp + 1;
+                rp = rp + 1 == cap ? 0 : rp + 1;
+                old_hi = rhi[rp * kBlock];
+                old_mid = rmid[rp * kBlock];
+                hi = max_num(hi, S);
+                lo = min_num(lo, S);
+                ++u1;
+                bool cross = fabs(S) > thr_flat;
+                if (t >= t_split)  // wave-uniform; not reached while every u/n_v stays below e
+                    cross = cross_past_e(cross, S, thr2, u1, ue, nv, l2nv);
+                brk = cross ? min(brk, t - n) : brk;
             }
-            brk = cross ? min(brk, t - n) : brk;
             if (EXPORT && a.mosum && active && in)
-                put_out(a.mosum, (int64_t)(t - n) * a.P + lane, monitor ? Sm * rscale : qnan,
+                put_out(a.mosum, (int64_t)(t - n) * a.P + lane, monitor && ok ? S * rscale : qnan,
                         a.out_f64);
         },
-        pre);
+        pre, [](const V*) {});
 
     if (bad) st = BFM_ST_NONFINITE;
     if (st == BFM_ST_OK && u1 == nv) st = BFM_ST_NO_MONITOR;
@@ -446,7 +514,7 @@ template <int K, int F, bool EXPLICIT>
 hipError_t launch_kf(const MaskedArgs& a, hipStream_t stream)
 {
     const dim3 grid((unsigned)((a.P + kBlock - 1) / kBlock));
-    const size_t lds = (size_t)a.cap * kBlock * sizeof(double);
+    const size_t lds = masked_periodic_lds_bytes(a.cap);
     if (a.resid || a.mosum)
         hipLaunchKernelGGL((masked_periodic_kernel<K, F, true, EXPLICIT>), grid, dim3(kBlock), lds,
                            stream, a);
@@ -481,6 +549,8 @@ hipError_t launch_mode(const MaskedArgs& a, int order, hipStream_t stream)
 }
 
 }  // namespace
+
+size_t masked_periodic_lds_bytes(int cap) { return (size_t)cap * kBlock * 6; }
 
 hipError_t launch_masked_periodic(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream)
 {
