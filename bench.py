@@ -8,6 +8,10 @@ steps (see paper_1807_01751_amd/synth.py).  Y is device-resident before the
 timed region; one step is one bfm_fit_monitor call over the whole tile
 (fit, sigma, MOSUM, boundary test, break index and magnitude), FP64 arithmetic.
 
+After the headline leg, the same tile with 25% of its observations missing
+(NaN: half independent, half cloud runs of 3-15 rows) is timed through the
+masked path (per-pixel Gram and Cholesky); it is reported under "masked".
+
 Prints one JSON line.  Run with --gpus 1 (the default); more GPUs are not
 supported by this benchmark.
 """
@@ -26,10 +30,21 @@ P, N, n, ORDER, H_FRAC, LAM, FREQ = 1 << 20, 400, 200, 3, 0.25, 2.5, 23.0
 HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_1807_01751_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
-TRAFFIC_FILE = os.path.join(PROFILES, "traffic_plain_1024x1024_N400.json")
-# The kernel bfm_fit_monitor launches for this workload (f = 23 is an integer
-# period and the window H = 50 >= 23, so the period-blocked kernel is used).
-KERNEL = "periodic_kernel<3, 23, false>"
+MISSING = 0.25
+# The kernels bfm_fit_monitor launches for the two legs (f = 23 is an integer
+# period, so the period-blocked kernels are used), the rocprofv3 summaries kept
+# for each, and the workload each is timed on.
+LEGS = {
+    "plain": {"kernel": "::periodic_kernel<3, 23, false>(",
+              "traffic": os.path.join(PROFILES, "traffic_plain_1024x1024_N400.json"),
+              "trace_md": os.path.join(PROFILES, "plain_periodic_k3_f23_1024x1024_N400_kernel_trace.md"),
+              "workload": "1024x1024 pixels, N=400"},
+    "masked": {"kernel": "::masked_periodic_kernel<3, 23, false, false>(",
+               "traffic": os.path.join(PROFILES, "traffic_masked_1024x1024_N400_nan25.json"),
+               "trace_md": os.path.join(PROFILES,
+                                        "masked_periodic_k3_f23_1024x1024_N400_nan25_kernel_trace.md"),
+               "workload": "1024x1024 pixels, N=400, 25% NaN"},
+}
 PROFILE_CMD = ("rocprofv3 {flags} -f csv -d <dir> -o run -- python3 bench.py --steps 10 "
                "--warmup 2 --no-cpu-baseline --copy-calibration")
 
@@ -48,11 +63,11 @@ def kernel_sha():
     return h.hexdigest()[:16]
 
 
-def traffic_per_launch():
+def traffic_per_launch(leg):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None
     when the kernel source changed since the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(LEGS[leg]["traffic"]) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -92,7 +107,7 @@ def _csv(path):
 
 def summarize_profiles(d):
     """Turn rocprofv3 CSV output of the three passes under ``d`` (trace/, fetch/,
-    write/) into the summaries kept in profiles/."""
+    write/) into the summaries kept in profiles/, one set per leg."""
     import glob
     import re
     P_ALG = (4 * N + 8) * P
@@ -101,47 +116,84 @@ def summarize_profiles(d):
         with open(os.path.join(d, sub + ".log")) as f:
             shas |= set(re.findall(r"kernel_sha=([0-9a-f]+)", f.read()))
     assert shas == {kernel_sha()}, f"profiles were taken on other sources: {shas}"
-    stats = [r for r in _csv(glob.glob(os.path.join(d, "trace", "*kernel_stats.csv"))[0])
-             if KERNEL in r["Name"]]
-    assert stats, "benchmark kernel missing from the trace"
-    st = stats[0]
-    per = {}
-    for counter, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
-        rows = _csv(glob.glob(os.path.join(d, sub, "*counter_collection.csv"))[0])
-        k = [float(r["Counter_Value"]) for r in rows if KERNEL in r["Kernel_Name"]]
-        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
-        calib = float(copies[-1]["Counter_Value"])  # the 1 GiB copy runs last
-        factor = (1 << 30) / (calib * 1024.0)       # bytes per counted byte
-        per[counter] = {"kib_per_dispatch": sum(k) / len(k), "dispatches": len(k),
-                        "copy_1GiB_kib": calib, "factor": factor}
-    hbm = sum(v["kib_per_dispatch"] * 1024.0 * v["factor"] for v in per.values())
-    avg_ns = float(st["AverageNs"])
-    traffic = {"kernel": KERNEL, "kernel_sha": kernel_sha(), "workload": "1024x1024 pixels, N=400",
-               "hbm_bytes_per_launch": round(hbm), "algorithmic_bytes_per_launch": P_ALG,
-               "traffic_over_algorithmic": hbm / P_ALG, "counters": per,
-               "commands": [PROFILE_CMD.format(flags="--pmc FETCH_SIZE"),
-                            PROFILE_CMD.format(flags="--pmc WRITE_SIZE")]}
+    trace = _csv(glob.glob(os.path.join(d, "trace", "*kernel_stats.csv"))[0])
+    counters = {sub: _csv(glob.glob(os.path.join(d, sub, "*counter_collection.csv"))[0])
+                for sub in ("fetch", "write")}
     os.makedirs(PROFILES, exist_ok=True)
-    with open(TRAFFIC_FILE, "w") as f:
-        json.dump(traffic, f, indent=1)
-    md = os.path.join(PROFILES, "plain_periodic_k3_f23_1024x1024_N400_kernel_trace.md")
-    with open(md, "w") as f:
-        f.write(f"# rocprofv3 kernel trace: {KERNEL}, 1024x1024 pixels, N=400\n\n")
-        f.write("Command (from the repository root, on one MI355X):\n\n    "
-                + PROFILE_CMD.format(flags="--kernel-trace --stats") + "\n\n")
-        f.write("| kernel | calls | average ns | min ns | max ns |\n|---|---|---|---|---|\n")
-        f.write(f"| {st['Name']} | {st['Calls']} | {avg_ns:.0f} | {st['MinNs']} | {st['MaxNs']} |\n\n")
-        f.write(f"Algorithmic bytes per launch: {P_ALG} (4N + 8 per pixel). At the average duration "
-                f"this is {P_ALG / avg_ns:.1f} GB/s ({P_ALG / avg_ns / HBM_PEAK_GBS:.3f} of 8 TB/s).\n\n")
-        f.write(f"HBM traffic (FETCH_SIZE and WRITE_SIZE passes, each scaled by its reading "
-                f"for a 1 GiB device copy): {hbm:.0f} B per launch = "
-                f"{hbm / P_ALG:.4f} x algorithmic.\n\n| counter | KiB per dispatch | "
-                f"1 GiB copy reads (KiB) | scale |\n|---|---|---|---|\n")
-        for c, v in per.items():
-            f.write(f"| {c} | {v['kib_per_dispatch']:.1f} | {v['copy_1GiB_kib']:.1f} | "
-                    f"{v['factor']:.4f} |\n")
-    print(md)
-    print(TRAFFIC_FILE)
+    for leg, spec in LEGS.items():
+        KERNEL = spec["kernel"]
+        stats = [r for r in trace if KERNEL in r["Name"]]
+        assert stats, f"{leg} kernel missing from the trace"
+        st = stats[0]
+        per = {}
+        for counter, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+            rows = counters[sub]
+            k = [float(r["Counter_Value"]) for r in rows if KERNEL in r["Kernel_Name"]]
+            copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+            calib = float(copies[-1]["Counter_Value"])  # the 1 GiB copy runs last
+            factor = (1 << 30) / (calib * 1024.0)       # bytes per counted byte
+            per[counter] = {"kib_per_dispatch": sum(k) / len(k), "dispatches": len(k),
+                            "copy_1GiB_kib": calib, "factor": factor}
+        hbm = sum(v["kib_per_dispatch"] * 1024.0 * v["factor"] for v in per.values())
+        avg_ns = float(st["AverageNs"])
+        traffic = {"kernel": KERNEL.strip(":("), "kernel_sha": kernel_sha(),
+                   "workload": spec["workload"],
+                   "hbm_bytes_per_launch": round(hbm), "algorithmic_bytes_per_launch": P_ALG,
+                   "traffic_over_algorithmic": hbm / P_ALG, "counters": per,
+                   "commands": [PROFILE_CMD.format(flags="--pmc FETCH_SIZE"),
+                                PROFILE_CMD.format(flags="--pmc WRITE_SIZE")]}
+        with open(spec["traffic"], "w") as f:
+            json.dump(traffic, f, indent=1)
+        with open(spec["trace_md"], "w") as f:
+            f.write(f"# rocprofv3 kernel trace: {KERNEL.strip(':(')}, {spec['workload']}\n\n")
+            f.write("Command (from the repository root, on one MI355X):\n\n    "
+                    + PROFILE_CMD.format(flags="--kernel-trace --stats") + "\n\n")
+            f.write("| kernel | calls | average ns | min ns | max ns |\n|---|---|---|---|---|\n")
+            f.write(f"| {st['Name']} | {st['Calls']} | {avg_ns:.0f} | {st['MinNs']} | "
+                    f"{st['MaxNs']} |\n\n")
+            f.write(f"Algorithmic bytes per launch: {P_ALG} (4N + 8 per pixel). At the average "
+                    f"duration this is {P_ALG / avg_ns:.1f} GB/s "
+                    f"({P_ALG / avg_ns / HBM_PEAK_GBS:.3f} of 8 TB/s).\n\n")
+            f.write(f"HBM traffic (FETCH_SIZE and WRITE_SIZE passes, each scaled by its reading "
+                    f"for a 1 GiB device copy): {hbm:.0f} B per launch = "
+                    f"{hbm / P_ALG:.4f} x algorithmic.\n\n| counter | KiB per dispatch | "
+                    f"1 GiB copy reads (KiB) | scale |\n|---|---|---|---|\n")
+            for c, v in per.items():
+                f.write(f"| {c} | {v['kib_per_dispatch']:.1f} | {v['copy_1GiB_kib']:.1f} | "
+                        f"{v['factor']:.4f} |\n")
+        print(spec["trace_md"])
+        print(spec["traffic"])
+
+
+def timed(step, steps, warmup, stream):
+    """Warm up, then time ``steps`` calls: wall clock over all of them and HIP
+    events around each launch on the stream the kernel runs on."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = sorted(a.elapsed_time(b) for a, b in ev)  # ms, per launch
+    return {"ms_per_step": wall * 1e3 / steps, "mean": sum(lat) / len(lat),
+            "p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]}
+
+
+def roofline(leg, mean_ms):
+    bytes_per_px = 4 * N + 4 + 4  # read FP32 y once; write int32 brk + FP32 mag
+    alg_bytes = bytes_per_px * P
+    achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_per_launch(leg),
+            "kernel": LEGS[leg]["kernel"].strip(":("), "algorithmic_bytes_per_launch": alg_bytes}
 
 
 def main():
@@ -185,27 +237,25 @@ def main():
         bfm.fit_monitor(Y, n=n, order=ORDER, freq=FREQ, h=H_FRAC, lam=LAM,
                         outputs=("brk", "mag"), out_dtype=torch.float32, out=out)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"bench: warmup {args.warmup} done; timing {args.steps} steps")
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
     stream = torch.cuda.current_stream(dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for a, b in ev:
-        a.record(stream)
-        step()
-        b.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    lat = sorted(a.elapsed_time(b) for a, b in ev)  # ms, per launch
-    ms_per_step = wall * 1e3 / args.steps
-    mean_lat = sum(lat) / len(lat)
-    p50 = lat[len(lat) // 2]
-    p99 = lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]
-    log(f"bench: {ms_per_step:.4f} ms/step wall, kernel mean {mean_lat:.4f} ms")
+    log(f"bench: plain leg, warmup {args.warmup}, timing {args.steps} steps")
+    tp = timed(step, args.steps, args.warmup, stream)
+    log(f"bench: {tp['ms_per_step']:.4f} ms/step wall, kernel mean {tp['mean']:.4f} ms")
+
+    # Masked leg: the same tile with NaN at 25% of (time, pixel) positions.
+    from paper_1807_01751_amd.synth import apply_missing, make_missing, split_rate
+    r = split_rate(MISSING)
+    Ym = apply_missing(Y.clone(), make_missing(N, P, iid=r, runs=r, seed=7, device=dev))
+    miss = float(torch.isnan(Ym).float().mean())
+
+    def mstep():
+        bfm.fit_monitor(Ym, n=n, order=ORDER, freq=FREQ, h=H_FRAC, lam=LAM, mask_mode=bfm.MASK_NAN,
+                        outputs=("brk", "mag"), out_dtype=torch.float32, out=out)
+
+    log(f"bench: masked leg ({miss:.3f} missing), warmup {args.warmup}, timing {args.steps} steps")
+    tm = timed(mstep, args.steps, args.warmup, stream)
+    log(f"bench: masked {tm['ms_per_step']:.4f} ms/step wall, kernel mean {tm['mean']:.4f} ms")
+    del Ym
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -215,12 +265,7 @@ def main():
         log("bench: copy calibration: 1 GiB read + 1 GiB written")
         del src, dst
 
-    bytes_per_px = 4 * N + 4 + 4  # read FP32 y once; write int32 brk + FP32 mag
-    alg_bytes = bytes_per_px * P
-    achieved = alg_bytes / (mean_lat * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_per_launch(),
-            "kernel": KERNEL, "algorithmic_bytes_per_launch": alg_bytes}
+    ms_per_step = tp["ms_per_step"]
     res = {"metric": METRIC, "value": round(P / (ms_per_step * 1e-3) / 1e6, 2), "unit": "Mpixel/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak",
@@ -230,7 +275,16 @@ def main():
                                   "h=0.25 (H=50), lambda=2.5, f=23, 20% planted steps",
                       "pixels": P, "n_obs": N, "n_hist": n, "p": 2 + 2 * ORDER,
                       "outputs": "brk int32 + mag f32", "parallelism": "single GPU"},
-           "p50_ms": round(p50, 5), "p99_ms": round(p99, 5), "roofline": roof}
+           "p50_ms": round(tp["p50"], 5), "p99_ms": round(tp["p99"], 5),
+           "roofline": roofline("plain", tp["mean"]),
+           "masked": {"value": round(P / (tm["ms_per_step"] * 1e-3) / 1e6, 2), "unit": "Mpixel/s",
+                      "ms_per_step": round(tm["ms_per_step"], 5), "p50_ms": round(tm["p50"], 5),
+                      "p99_ms": round(tm["p99"], 5), "dtype": "f64",
+                      "config": {"workload": "masked BFAST Monitor, the same tile with "
+                                             f"{100 * MISSING:.0f}% NaN (half iid, half cloud runs "
+                                             "of 3-15 rows), per-pixel Gram and Cholesky",
+                                 "missing_fraction": round(miss, 4)},
+                      "roofline": roofline("masked", tm["mean"])}}
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
         res["cpu_baseline"] = cpu_baseline(Y, args.cpu_seconds)

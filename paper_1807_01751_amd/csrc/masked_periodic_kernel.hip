@@ -78,6 +78,10 @@ __device__ __noinline__ bool cross_past_e(bool cross_flat, double S, double thr2
     return s2 > thr2 * log((double)u / (double)nv);
 }
 
+// Ring slots of the blocked kernel for the general kernel's ring capacity (the
+// longest window plus one): the longest window, at least one.
+__host__ __device__ constexpr int ring_slots(int cap) { return cap > 2 ? cap - 1 : 1; }
+
 // A residual in a 6-byte ring slot: the low 16 of its 52 mantissa bits are
 // cleared (relative change below 2^-36) and the value stored is the value
 // returned, the one the MOSUM adds.
@@ -210,7 +214,8 @@ masked_periodic_kernel(MaskedArgs a)
     const int64_t pix = (int64_t)blockIdx.x * kBlock + tid;
     const bool active = pix < a.P;
     const uint32_t lane = (uint32_t)(active ? pix : a.P - 1);
-    const int n = a.n, N = a.N, cap = a.cap;
+    const int n = a.n, N = a.N;
+    const int cap = ring_slots(a.cap);  // the longest window: rows are written only when observed
     const ctab ph = as_const(a.ph);
     uint32_t* const rhi = ring_hi + tid;
     uint16_t* const rmid = reinterpret_cast<uint16_t*>(ring_hi + cap * kBlock) + tid;
@@ -227,7 +232,7 @@ masked_periodic_kernel(MaskedArgs a)
     double yy = 0.0, Bd = 0.0;
     uint32_t cnt = 0u, zs = 0u, ymaxb = 0u;
     bool bad = false;
-    int wp = 0;  // next ring slot; the ring has one slot more than the longest window
+    int wp = 0;  // next ring slot
     uint32_t inc = 1u;
     double bd = 0.0;
     // Centring constant c: the first observed history value, found in the first
@@ -402,23 +407,42 @@ masked_periodic_kernel(MaskedArgs a)
     }
 
     // ---- the last H observed history values become residuals ----
+    // Four slots per step, so that their phase-table gathers are in flight
+    // together; the wave stops at its largest window.
     double S = 0.0;
-    for (int i = 0; i < cap - 1; ++i) {
-        int slot = wp - H + i;
-        slot += slot < 0 ? cap : 0;
-        if (monitor && i < H) {
-            const float y = __uint_as_float(rhi[slot * kBlock]);
-            const int t = rmid[slot * kBlock];
-            const int r = t % F;
-            double pr = fma(beta[1], ((double)t - c0) * inv_n, beta[0] + c);
-            const double* hr = a.ph + r * NT;
+    int hmax = monitor ? H : 0;
 #pragma unroll
-            for (int j = 1; j <= K; ++j) {
-                pr = fma(beta[2 * j], hr[2 * (j - 1)], pr);
-                pr = fma(beta[2 * j + 1], hr[2 * (j - 1) + 1], pr);
+    for (int o = 32; o >= 1; o >>= 1) hmax = max(hmax, __shfl_xor(hmax, o));
+    hmax = __builtin_amdgcn_readfirstlane(hmax);
+    for (int i0 = 0; i0 < hmax; i0 += 4) {
+        int slot[4], t[4];
+        float y[4];
+        double hr[4][2 * K + 1];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {  // slots past the lane's window read slot 0, unused
+            slot[k] = wp - H + i0 + k;
+            slot[k] += slot[k] < 0 ? cap : 0;
+            slot[k] = monitor && i0 + k < H ? slot[k] : 0;
+            y[k] = __uint_as_float(rhi[slot[k] * kBlock]);
+            t[k] = rmid[slot[k] * kBlock];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double* row = a.ph + (t[k] % F) * NT;
+#pragma unroll
+            for (int j = 0; j < 2 * K; ++j) hr[k][j] = row[j];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (monitor && i0 + k < H) {
+                double pr = fma(beta[1], ((double)t[k] - c0) * inv_n, beta[0] + c);
+#pragma unroll
+                for (int j = 1; j <= K; ++j) {
+                    pr = fma(beta[2 * j], hr[k][2 * (j - 1)], pr);
+                    pr = fma(beta[2 * j + 1], hr[k][2 * (j - 1) + 1], pr);
+                }
+                S += ring_store(rhi, rmid, slot[k], (double)y[k] - pr);
             }
-            const double res = ring_store(rhi, rmid, slot, (double)y - pr);
-            S += res;
         }
     }
 
@@ -515,6 +539,7 @@ hipError_t launch_kf(const MaskedArgs& a, hipStream_t stream)
 {
     const dim3 grid((unsigned)((a.P + kBlock - 1) / kBlock));
     const size_t lds = masked_periodic_lds_bytes(a.cap);
+    if (a.n >= 65536) return hipErrorInvalidValue;  // history rows are kept as 16-bit indices
     if (a.resid || a.mosum)
         hipLaunchKernelGGL((masked_periodic_kernel<K, F, true, EXPLICIT>), grid, dim3(kBlock), lds,
                            stream, a);
@@ -550,7 +575,7 @@ hipError_t launch_mode(const MaskedArgs& a, int order, hipStream_t stream)
 
 }  // namespace
 
-size_t masked_periodic_lds_bytes(int cap) { return (size_t)cap * kBlock * 6; }
+size_t masked_periodic_lds_bytes(int cap) { return (size_t)ring_slots(cap) * kBlock * 6; }
 
 hipError_t launch_masked_periodic(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream)
 {
