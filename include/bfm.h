@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define BFM_VERSION 1
+#define BFM_VERSION 2
 
 /* return codes */
 #define BFM_SUCCESS 0
@@ -52,6 +52,11 @@ extern "C" {
 
 /* arithmetic of the computation */
 #define BFM_PREC_FP64 0
+
+/* storage type of the series Y (bfm_fit_monitor_typed) */
+#define BFM_Y_F32 0  /* IEEE float32                                        */
+#define BFM_Y_BF16 1 /* bfloat16: the high 16 bits of a float32, as uint16  */
+#define BFM_Y_F16 2  /* IEEE binary16 (11 significant bits), as uint16      */
 
 /* element type of the floating-point outputs */
 #define BFM_OUT_F32 0
@@ -166,6 +171,26 @@ int bfm_destroy(bfm_ctx *ctx);
 int bfm_fit_monitor(bfm_ctx *ctx, const bfm_params *prm, const float *Y, int64_t P,
                     int64_t ld, const uint8_t *valid, int64_t ldv, const bfm_outputs *out,
                     void *stream);
+
+/*
+ * bfm_fit_monitor with the series stored as y_dtype (BFM_Y_F32, BFM_Y_BF16 or
+ * BFM_Y_F16).  A 16-bit series halves the bytes streamed from HBM, the bound of
+ * the path (Section 5 proposes lowering the precision of the data to cut the
+ * volume that has to be moved).  Each observation is decoded exactly to
+ * float32 and the arithmetic stays FP64, so the results are those of
+ * bfm_fit_monitor on the decoded series; what the narrower storage costs is
+ * the rounding of the data itself (BF16 keeps 8 significant bits, FP16 11).
+ * ld and ldv count elements.  16-bit series are served by the period-blocked
+ * kernels: f in {12, 23, 24} and order <= 4, and additionally on the plain path
+ * a window H >= f and a full-rank history design, on the missing-value paths
+ * n_hist <= 8192 and ld * 4 * f < 2^31; other parameter sets return
+ * BFM_E_UNSUPPORTED.
+ * Errors: those of bfm_fit_monitor, BFM_E_INVAL for an unknown y_dtype, and
+ * BFM_E_UNSUPPORTED as above.
+ */
+int bfm_fit_monitor_typed(bfm_ctx *ctx, const bfm_params *prm, const void *Y, int32_t y_dtype,
+                          int64_t P, int64_t ld, const uint8_t *valid, int64_t ldv,
+                          const bfm_outputs *out, void *stream);
 
 /*
  * Host-only view of the shared operators the plain path streams against, for

@@ -22,6 +22,8 @@ SUCCESS = 0
 E_INVAL, E_LAYOUT, E_NOMEM, E_NODEVICE, E_HIP, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
 MASK_NONE, MASK_NAN, MASK_EXPLICIT = 0, 1, 2
 PREC_FP64 = 0
+Y_F32, Y_BF16, Y_F16 = 0, 1, 2
+_Y_DTYPES = {torch.float32: Y_F32, torch.bfloat16: Y_BF16, torch.float16: Y_F16}
 OUT_F32, OUT_F64 = 0, 1
 ST_OK, ST_NONFINITE, ST_INSUFFICIENT, ST_RANK_DEFICIENT, ST_DEGENERATE_SIGMA, ST_NO_MONITOR = range(6)
 
@@ -30,7 +32,7 @@ _ERRNAMES = {E_INVAL: "BFM_E_INVAL", E_LAYOUT: "BFM_E_LAYOUT", E_NOMEM: "BFM_E_N
 
 # Every symbol include/bfm.h declares.
 EXPORTS = ("bfm_version", "bfm_last_error", "bfm_check_params", "bfm_create", "bfm_destroy",
-           "bfm_fit_monitor", "bfm_host_operators")
+           "bfm_fit_monitor", "bfm_fit_monitor_typed", "bfm_host_operators")
 
 
 class BfmError(RuntimeError):
@@ -88,6 +90,8 @@ def load():
     lib.bfm_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
     lib.bfm_destroy.argtypes = [vp]
     lib.bfm_fit_monitor.argtypes = [vp, P_, vp, i64, i64, vp, i64, ctypes.POINTER(Outputs), vp]
+    lib.bfm_fit_monitor_typed.argtypes = [vp, P_, vp, ctypes.c_int32, i64, i64, vp, i64,
+                                          ctypes.POINTER(Outputs), vp]
     lib.bfm_host_operators.argtypes = [P_, vp, vp, vp, vp]
     _lib = lib
     return lib
@@ -162,7 +166,8 @@ def fit_monitor(Y: torch.Tensor, *, n: int, order: int = 3, freq: float = 23.0, 
                 valid: torch.Tensor | None = None, outputs=("brk", "mag"),
                 out_dtype: torch.dtype = torch.float64, out: dict | None = None,
                 stream: torch.cuda.Stream | None = None) -> dict:
-    """bfm_fit_monitor on a device-resident float32 series block.
+    """bfm_fit_monitor on a device-resident series block (float32, bfloat16 or
+    float16, through bfm_fit_monitor_typed).
 
     ``Y`` is time-major: shape (N, P) with unit stride along pixels (or the
     (P, N) transpose view of such a block).  ``outputs`` names the arrays to
@@ -170,8 +175,8 @@ def fit_monitor(Y: torch.Tensor, *, n: int, order: int = 3, freq: float = 23.0, 
     preallocated tensors for them.  Work is enqueued on ``stream`` (default: the
     current stream) and the call returns without synchronising.
     """
-    if Y.dtype != torch.float32 or Y.device.type != "cuda":
-        raise ValueError("Y must be a float32 tensor on a HIP device")
+    if Y.dtype not in _Y_DTYPES or Y.device.type != "cuda":
+        raise ValueError("Y must be a float32, bfloat16 or float16 tensor on a HIP device")
     Y, N, P, ld = _series_layout(Y)
     dev = Y.device.index if Y.device.index is not None else torch.cuda.current_device()
     prm = make_params(N, n, order, freq, h, h_window, lam, mask_mode)
@@ -203,7 +208,8 @@ def fit_monitor(Y: torch.Tensor, *, n: int, order: int = 3, freq: float = 23.0, 
             raise ValueError("valid must be a uint8 tensor laid out like Y")
         vptr = valid.data_ptr()
     s = stream if stream is not None else torch.cuda.current_stream(Y.device)
-    rc = load().bfm_fit_monitor(context(dev), ctypes.byref(prm), Y.data_ptr(), P, ld, vptr, ldv,
-                                ctypes.byref(o), s.cuda_stream)
+    y_dtype = _Y_DTYPES[Y.dtype]
+    rc = load().bfm_fit_monitor_typed(context(dev), ctypes.byref(prm), Y.data_ptr(), y_dtype, P, ld,
+                                      vptr, ldv, ctypes.byref(o), s.cuda_stream)
     _raise(rc)
     return res

@@ -97,7 +97,7 @@ struct DeviceGuard {
 };
 
 // Missing-value modes: per-pixel masked fit (csrc/masked_kernel.hip).
-int fit_masked(bfm_ctx* ctx, const bfm_params& p, const float* Y, int64_t P, int64_t ld,
+int fit_masked(bfm_ctx* ctx, const bfm_params& p, const void* Y, int y_dtype, int64_t P, int64_t ld,
                const uint8_t* valid, int64_t ldv, const bfm_outputs& out, hipStream_t s)
 {
     bfm_ctx::Key key{p.n_obs, p.n_hist, p.order, p.h_window, p.freq, p.h_frac, 0.0};
@@ -122,12 +122,16 @@ int fit_masked(bfm_ctx* ctx, const bfm_params& p, const float* Y, int64_t P, int
     const int64_t lim = (int64_t)1 << 31;
     const bool blocked = ops.F > 0 && ld * 4 * ops.F < lim &&
                          (p.mask_mode != BFM_MASK_EXPLICIT || ldv * ops.F < lim);
+    if (y_dtype != BFM_Y_F32 && !blocked)
+        return fail(BFM_E_UNSUPPORTED, "a 16-bit series needs f in {12, 23, 24}, n_hist <= %d and "
+                    "ld * 4 * f < 2^31 on the missing-value path", bfm::kMaskedPeriodicMaxHist);
     const size_t lds = blocked ? bfm::masked_periodic_lds_bytes(ops.cap) : bfm::masked_lds_bytes(ops.cap);
     if (lds > ctx->max_lds)
         return fail(BFM_E_UNSUPPORTED, "window H=%d needs %zu B of LDS per workgroup (max %zu)",
                     ops.Hmax, lds, ctx->max_lds);
     bfm::MaskedArgs a{};
     a.Y = Y;
+    a.y_dtype = y_dtype;
     a.ld = ld;
     a.valid = valid;
     a.ldv = ldv;
@@ -225,7 +229,17 @@ int bfm_host_operators(const bfm_params* prm, double* q, double* w, double* bnd,
 int bfm_fit_monitor(bfm_ctx* ctx, const bfm_params* prm, const float* Y, int64_t P, int64_t ld,
                     const uint8_t* valid, int64_t ldv, const bfm_outputs* out, void* stream)
 {
+    return bfm_fit_monitor_typed(ctx, prm, Y, BFM_Y_F32, P, ld, valid, ldv, out, stream);
+}
+
+int bfm_fit_monitor_typed(bfm_ctx* ctx, const bfm_params* prm, const void* Y, int32_t y_dtype,
+                          int64_t P, int64_t ld, const uint8_t* valid, int64_t ldv,
+                          const bfm_outputs* out, void* stream)
+{
     if (!ctx) return fail(BFM_E_INVAL, "ctx is NULL");
+    if (y_dtype != BFM_Y_F32 && y_dtype != BFM_Y_BF16 && y_dtype != BFM_Y_F16)
+        return fail(BFM_E_INVAL, "unknown y_dtype %d", y_dtype);
+    const int narrow = y_dtype != BFM_Y_F32;  // 16-bit storage: period-blocked kernels only
     int rc = check(prm, P, ld);
     if (rc) return rc;
     if (!out) return fail(BFM_E_INVAL, "out is NULL");
@@ -246,7 +260,7 @@ int bfm_fit_monitor(bfm_ctx* ctx, const bfm_params* prm, const float* Y, int64_t
 
     std::lock_guard<std::mutex> lock(ctx->mu);
     DeviceGuard g(ctx->device);
-    if (p.mask_mode != BFM_MASK_NONE) return fit_masked(ctx, p, Y, P, ld, valid, ldv, *out, s);
+    if (p.mask_mode != BFM_MASK_NONE) return fit_masked(ctx, p, Y, y_dtype, P, ld, valid, ldv, *out, s);
     bfm_ctx::Key key{p.n_obs, p.n_hist, p.order, p.h_window, p.freq, p.h_frac, p.lambda};
     auto it = ctx->plain.find(key);
     if (it == ctx->plain.end()) {
@@ -297,8 +311,8 @@ int bfm_fit_monitor(bfm_ctx* ctx, const bfm_params* prm, const float* Y, int64_t
         global_st = BFM_ST_RANK_DEFICIENT;
     hipError_t e;
     if (global_st != BFM_ST_OK) {
-        e = bfm::launch_fill_status(Y, ld, P, p.n_obs, p.n_hist, np, global_st, *out, p.mask_mode,
-                                    valid, ldv, s);
+        e = bfm::launch_fill_status(Y, y_dtype, ld, P, p.n_obs, p.n_hist, np, global_st, *out,
+                                    p.mask_mode, valid, ldv, s);
         return e == hipSuccess ? BFM_SUCCESS : hip_fail(e, "fill_status launch");
     }
     const size_t lds = (size_t)ops.H * bfm::kPlainBlock * sizeof(float);
@@ -308,6 +322,7 @@ int bfm_fit_monitor(bfm_ctx* ctx, const bfm_params* prm, const float* Y, int64_t
     if (it->second.per.F > 0) {
         bfm::PeriodicArgs a{};
         a.Y = Y;
+        a.y_dtype = y_dtype;
         a.ld = ld;
         a.P = P;
         a.tab = it->second.pdev;
@@ -330,10 +345,13 @@ int bfm_fit_monitor(bfm_ctx* ctx, const bfm_params* prm, const float* Y, int64_t
         if (e != hipSuccess) return hip_fail(e, "periodic kernel launch");
         return BFM_SUCCESS;
     }
+    if (narrow)
+        return fail(BFM_E_UNSUPPORTED, "a 16-bit series needs f in {12, 23, 24}, order <= %d and a "
+                    "window H >= f on this path", bfm::kPeriodicMaxOrder);
     const double* d = it->second.dev;
     const size_t nq = ops.q.size(), nw = ops.w.size(), nb = ops.bnd.size();
     bfm::PlainArgs a{};
-    a.Y = Y;
+    a.Y = static_cast<const float*>(Y);
     a.ld = ld;
     a.P = P;
     a.q = d;

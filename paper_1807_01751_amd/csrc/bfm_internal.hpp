@@ -106,7 +106,8 @@ hipError_t launch_plain(const PlainArgs& a, int p, hipStream_t stream);
 
 // Arguments of the period-blocked plain kernel.
 struct PeriodicArgs {
-    const float* Y;
+    const void* Y;       // element type y_dtype (BFM_Y_*)
+    int y_dtype;
     int64_t ld;
     int64_t P;
     const double* tab;   // rt | ri | hh | wh | bnd
@@ -122,10 +123,12 @@ struct PeriodicArgs {
     int out_f64;
 };
 hipError_t launch_periodic(const PeriodicArgs& a, int order, int F, hipStream_t stream);
+hipError_t launch_periodic_16(const PeriodicArgs& a, int order, int F, hipStream_t stream);
 
 // Arguments of the masked kernel (by value; every pointer is device memory).
 struct MaskedArgs {
-    const float* Y;
+    const void* Y;         // element type y_dtype (BFM_Y_*; 16-bit types: period-blocked kernel only)
+    int y_dtype;
     int64_t ld;
     const uint8_t* valid;  // EXPLICIT mode only
     int64_t ldv;
@@ -148,13 +151,14 @@ struct MaskedArgs {
 
 hipError_t launch_masked(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
 hipError_t launch_masked_periodic(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
+hipError_t launch_masked_periodic_16(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
 size_t masked_periodic_lds_bytes(int cap);
 size_t masked_lds_bytes(int cap);
 
 // Every pixel gets `st` (or NONFINITE if one of its used observations is not
 // finite), brk = -1 and NaN floating outputs: used when the parameters make
 // every pixel degenerate (history too short, rank-deficient shared design).
-hipError_t launch_fill_status(const float* Y, int64_t ld, int64_t P, int N, int n, int p,
+hipError_t launch_fill_status(const void* Y, int y_dtype, int64_t ld, int64_t P, int N, int n, int p,
                               uint8_t st, const bfm_outputs& out, int mask_mode,
                               const uint8_t* valid, int64_t ldv, hipStream_t stream);
 

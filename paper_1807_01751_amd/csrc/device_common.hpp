@@ -37,6 +37,36 @@ __device__ __forceinline__ float load_obs(const float* row, uint32_t lane_bytes)
         __builtin_amdgcn_raw_buffer_load_b32(row_rsrc(row), (int)lane_bytes, 0, kLoadNT));
 }
 
+// A BF16 observation as stored: the high half of the float32 of the same value
+// (decoding is exact: the low 16 bits of the float are zero).
+struct bf16_t {
+    uint16_t bits;
+};
+
+// An IEEE binary16 observation as stored (decoding to float32 is exact).
+struct f16_t {
+    uint16_t bits;
+};
+
+__device__ __forceinline__ float decode(bf16_t, uint32_t b) { return __uint_as_float(b << 16); }
+__device__ __forceinline__ float decode(f16_t, uint32_t b)
+{
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)b);
+}
+
+__device__ __forceinline__ float to_float(float v) { return v; }
+__device__ __forceinline__ float to_float(bf16_t v) { return decode(v, v.bits); }
+__device__ __forceinline__ float to_float(f16_t v) { return decode(v, v.bits); }
+
+// 16-bit storage types: one 2-byte load per lane, decoded in a register.
+template <typename T>
+__device__ __forceinline__ float load_obs(const T* row, uint32_t lane_bytes)
+{
+    static_assert(sizeof(T) == 2, "16-bit storage types only");
+    const uint32_t b = __builtin_amdgcn_raw_buffer_load_b16(row_rsrc(row), (int)lane_bytes, 0, kLoadNT);
+    return decode(T{}, b);
+}
+
 __device__ __forceinline__ uint32_t load_flag(const uint8_t* row, uint32_t lane)
 {
     return __builtin_amdgcn_raw_buffer_load_b8(row_rsrc(row), (int)lane, 0, kLoadNT);
@@ -56,18 +86,21 @@ __device__ __forceinline__ void put_out(void* base, int64_t idx, double v, int f
         put<float>(base, idx, v);
 }
 
-// Cursor over one pixel column of the time-major series.
-struct ObsCursor {
+// Cursor over one pixel column of the time-major series (stored as T: float or
+// bf16_t); it hands out float32 values.
+template <typename T>
+struct ObsCursorT {
     using value_type = float;
-    const float* row;  // wave-uniform address of the current time row
+    const T* row;  // wave-uniform address of the current time row
     int64_t ld;
-    uint32_t lane_bytes;
+    uint32_t lane_bytes;  // lane * sizeof(T)
     __device__ __forceinline__ value_type load(int u) const
     {
         return load_obs(row + (int64_t)u * ld, lane_bytes);
     }
     __device__ __forceinline__ void advance(int k) { row += (int64_t)k * ld; }
 };
+using ObsCursor = ObsCursorT<float>;
 
 // An observation and its caller-supplied validity flag (nonzero = observed).
 struct FlaggedObs {

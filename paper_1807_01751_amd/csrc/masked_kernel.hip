@@ -51,6 +51,7 @@ __global__ __launch_bounds__(kMaskedBlock) void masked_kernel(MaskedArgs a)
     const ctab x = as_const(a.x);
     const ctab g = as_const(a.g);
     double* const myring = ring + tid;
+    const float* const Y = static_cast<const float*>(a.Y);
 
     double c = 0.0, cnt = 0.0, yy = 0.0;
     bool have_c = false, bad = false;
@@ -82,10 +83,10 @@ __global__ __launch_bounds__(kMaskedBlock) void masked_kernel(MaskedArgs a)
         wp = used ? (wp + 1 == cap ? 0 : wp + 1) : wp;
     };
     if (EXPLICIT) {
-        stream_rows<kMU>(FlaggedCursor{a.Y, a.valid, ld, a.ldv, lane}, 0, n,
+        stream_rows<kMU>(FlaggedCursor{Y, a.valid, ld, a.ldv, lane}, 0, n,
                          [&](int t, FlaggedObs o) { hist_row(t, o.y, o.ok != 0); });
     } else {
-        stream_rows<kMU>(ObsCursor{a.Y, ld, lane * 4u}, 0, n,
+        stream_rows<kMU>(ObsCursor{Y, ld, lane * 4u}, 0, n,
                          [&](int t, float v) { hist_row(t, v, isfinite(v)); });
     }
 
@@ -178,11 +179,11 @@ __global__ __launch_bounds__(kMaskedBlock) void masked_kernel(MaskedArgs a)
                     used && monitor ? S / scale : __builtin_nan(""), a.out_f64);
     };
     if (EXPLICIT) {
-        stream_rows<kMU>(FlaggedCursor{a.Y + (int64_t)n * ld, a.valid + (int64_t)n * a.ldv, ld,
+        stream_rows<kMU>(FlaggedCursor{Y + (int64_t)n * ld, a.valid + (int64_t)n * a.ldv, ld,
                                        a.ldv, lane},
                          n, N, [&](int t, FlaggedObs o) { mon_row(t, o.y, o.ok != 0); });
     } else {
-        stream_rows<kMU>(ObsCursor{a.Y + (int64_t)n * ld, ld, lane * 4u}, n, N,
+        stream_rows<kMU>(ObsCursor{Y + (int64_t)n * ld, ld, lane * 4u}, n, N,
                          [&](int t, float v) { mon_row(t, v, isfinite(v)); });
     }
     if (bad) st = BFM_ST_NONFINITE;
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(kMaskedBlock) void masked_kernel(MaskedArgs a)
     if (EXPORT) {
         if (a.resid) {
             for (int t = 0; t < N; ++t) {
-                const float v = a.Y[(int64_t)t * ld + pix];
+                const float v = Y[(int64_t)t * ld + pix];
                 const bool used = EXPLICIT ? a.valid[(int64_t)t * a.ldv + pix] != 0 : isfinite(v);
                 double r = qnan;
                 if (have_fit && used) {

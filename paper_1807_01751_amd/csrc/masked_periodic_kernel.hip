@@ -1,586 +1,14 @@
-// Period-blocked masked kernel of BFAST Monitor for gfx950 (FP64 arithmetic):
-// pixels with missing observations when f is an integer number of rows F.
-//
-// Same reading of missing values as the general masked kernel: observed values
-// in time order form the series, design rows keep their original time, and the
-// window, the normaliser and the boundary use compacted counts (H = floor(h
-// n_v), sqrt(n_v), u/n_v).  With f = F rows the harmonic regressors of Eq. 2
-// repeat every F rows, so for row t = F b + r (phase r, block b) every entry of
-// the per-pixel Gram matrix sum_t w_t x~_t x~_t' follows from two integers per
-// phase, W_r (observed rows) and Q_r (sum of their block indices), and one per
-// pixel, sum w_t b_t^2: one packed integer add per row replaces the 2 + 6k
-// masked FP64 sums of the general kernel.  The right-hand side needs one FP64
-// sum per phase, A_r = sum w_t (y_t - c), plus sum w_t b_t (y_t - c).
-//
-// One lane owns one pixel and streams its series once, time-major, in blocks
-// of F rows aligned to multiples of F, so a row's phase is a compile-time
-// register index:
-//   history        W_r, Q_r, A_r, yy; (t, y_t) of each observed row goes to a
-//                  per-lane LDS ring.
-//   fit            Gram matrix from the phase sums (products of harmonics by
-//                  product-to-sum identities), Cholesky, beta, RSS = yy - ||z||^2.
-//   window start   the last H observed history values become residuals.
-//   monitoring     r_t = y_t - (P_r + gamma b): one FP64 subtract per row, with
-//                  P_r the fitted value at phase r in block 0 (constant, trend
-//                  and harmonics) and gamma the trend step per block; the ring
-//                  gives back the residual H observations earlier; boundary
-//                  test of Eq. 4 at the compacted position.
-#include <climits>
-#include <cmath>
-
-#include "bfm_internal.hpp"
-#include "device_common.hpp"
-#include "masked_common.hpp"
-
-// Every fused multiply-add below is written out: the template variants (with or
-// without exports, NaN or explicit masks) then round identically.
-#pragma clang fp contract(off)
+// Period-blocked masked kernel, float32 series (template in masked_periodic_kernel.hpp).
+#include "masked_periodic_kernel.hpp"
 
 namespace bfm {
-namespace {
-
-using namespace dev;
-
-constexpr int kBlock = 64;           // one wave per workgroup
-constexpr uint32_t kCountBits = 12;  // acc_r = W_r + (Q_r << 12)
-constexpr uint32_t kCountMask = (1u << kCountBits) - 1;
-
-// max and min of a running extreme and a value that is either a number or the
-// quiet NaN 0x7ff8...: in IEEE mode the hardware returns the other operand for a
-// quiet NaN, so the compiler's quieting of the operands is not needed.
-__device__ __forceinline__ double max_num(double a, double b)
-{
-    double r;
-    asm volatile("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-__device__ __forceinline__ double min_num(double a, double b)
-{
-    double r;
-    asm volatile("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-
-// Boundary test of Eq. 4 past e for one lane: |S| > lambda scale sqrt(ln(u/n_v)),
-// squared: S^2 > thr2 ln(u/n_v).  Called only for rows where some lane of the
-// wave may be past e; cross_flat (|S| > lambda scale) is necessary for a
-// crossing.  The hardware log2 in FP32 decides every case whose margin exceeds
-// 1e-5 (its error is below 1e-6 of ln(u/n_v) >= 1); the rest take the FP64
-// logarithm.
-__device__ __noinline__ bool cross_past_e(bool cross_flat, double S, double thr2, int u, int ue, int nv,
-                                          float l2nv)
-{
-    if (!cross_flat || u <= ue) return cross_flat;
-    const double s2 = S * S;
-    const double tl = thr2 * (double)((__log2f((float)u) - l2nv) * 0.69314718f);
-    if (s2 > tl * (1.0 + 1e-5)) return true;
-    if (!(s2 > tl * (1.0 - 1e-5))) return false;
-    return s2 > thr2 * log((double)u / (double)nv);
-}
-
-// Ring slots of the blocked kernel for the general kernel's ring capacity (the
-// longest window plus one): the longest window, at least one.
-__host__ __device__ constexpr int ring_slots(int cap) { return cap > 2 ? cap - 1 : 1; }
-
-// A residual in a 6-byte ring slot: the low 16 of its 52 mantissa bits are
-// cleared (relative change below 2^-36) and the value stored is the value
-// returned, the one the MOSUM adds.
-__device__ __forceinline__ double ring_store(uint32_t* hi, uint16_t* mid, int slot, double r)
-{
-    const uint64_t b = (uint64_t)__double_as_longlong(r) & ~(uint64_t)0xffff;
-    hi[slot * kBlock] = (uint32_t)(b >> 32);
-    mid[slot * kBlock] = (uint16_t)(b >> 16);
-    return __longlong_as_double((long long)b);
-}
-__device__ __forceinline__ double ring_value(uint32_t hi, uint16_t mid)
-{
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | ((uint64_t)mid << 16)));
-}
-
-__device__ __forceinline__ bool observed(float v) { return isfinite(v); }
-__device__ __forceinline__ bool observed(FlaggedObs o) { return o.ok != 0; }
-__device__ __forceinline__ float value(float v) { return v; }
-__device__ __forceinline__ float value(FlaggedObs o) { return o.y; }
-
-// Streams rows [t0, t1) in blocks of F rows aligned to multiples of F, two
-// blocks ahead of the arithmetic in three register buffers used in turn (the
-// loads of a wave must cover the memory latency: the LDS ring limits how many
-// waves share a compute unit).  Every block runs the same unrolled code: a row
-// of the block outside [t0, t1) is passed with in = false (a masked-path body
-// treats it as missing), and its load reads the nearest row inside instead.
-// init(buf) sees the first block before any row of it runs; pre(tb) runs before
-// the rows of block tb.
-template <int F, typename At, typename Body, typename Pre, typename Init>
-__device__ __forceinline__ void stream_blocks(At at, int t0, int t1, Body&& body, Pre&& pre, Init&& init)
-{
-    using V = typename decltype(at(0))::value_type;
-    if (t0 >= t1) return;
-    auto load = [&](V* buf, int tb) {
-        const auto cur = at(tb);
-        const int first = t0 - tb, last = t1 - 1 - tb;
-#pragma unroll
-        for (int u = 0; u < F; ++u) buf[u] = cur.load(u < first ? first : (u < last ? u : last));
-    };
-    auto run = [&](V* buf, int tb) {
-        pre(tb);
-        const int lo = t0 - tb > 0 ? t0 - tb : 0, hi = t1 - tb < F ? t1 - tb : F;
-        const uint32_t in = ((1u << hi) - 1u) & ~((1u << lo) - 1u);  // rows of the block in range
-#pragma unroll
-        for (int u = 0; u < F; ++u) body(u, tb + u, buf[u], ((in >> u) & 1u) != 0);
-    };
-    V a[F], b[F], c[F];
-    int tb = t0 - t0 % F;
-    load(a, tb);
-    if (tb + F < t1) load(b, tb + F);
-    init(static_cast<const V*>(a));
-    for (;;) {
-        if (tb + 2 * F < t1) load(c, tb + 2 * F);
-        run(a, tb);
-        tb += F;
-        if (tb >= t1) break;
-        if (tb + 2 * F < t1) load(a, tb + 2 * F);
-        run(b, tb);
-        tb += F;
-        if (tb >= t1) break;
-        if (tb + 2 * F < t1) load(b, tb + 2 * F);
-        run(c, tb);
-        tb += F;
-        if (tb >= t1) break;
-    }
-}
-
-// Rows tb, tb + 1, ... of the series from one buffer resource based at row tb:
-// row u of the block is at byte offset u * ld * 4 (a scalar offset), the lane's
-// pixel at lane * 4.  The host keeps F rows of offsets below 2^31.
-struct ObsBlock {
-    using value_type = float;
-    __amdgpu_buffer_rsrc_t y;
-    uint32_t ld4, lane_bytes;
-    __device__ __forceinline__ value_type load(int u) const
-    {
-        return __uint_as_float(
-            __builtin_amdgcn_raw_buffer_load_b32(y, (int)lane_bytes, (int)((uint32_t)u * ld4), kLoadNT));
-    }
-};
-
-// The same with the caller's validity flags (one byte per pixel and row).
-struct FlaggedBlock {
-    using value_type = FlaggedObs;
-    __amdgpu_buffer_rsrc_t y, f;
-    uint32_t ld4, ldv, lane;
-    __device__ __forceinline__ value_type load(int u) const
-    {
-        return {__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(y, (int)(lane * 4u),
-                                                                     (int)((uint32_t)u * ld4), kLoadNT)),
-                __builtin_amdgcn_raw_buffer_load_b8(f, (int)lane, (int)((uint32_t)u * ldv), kLoadNT)};
-    }
-};
-
-template <bool EXPLICIT>
-struct CursorOf {
-    using type = ObsBlock;
-    __device__ static type at(const MaskedArgs& a, int t, uint32_t lane)
-    {
-        return ObsBlock{row_rsrc(a.Y + (int64_t)t * a.ld), (uint32_t)a.ld * 4u, lane * 4u};
-    }
-};
-template <>
-struct CursorOf<true> {
-    using type = FlaggedBlock;
-    __device__ static type at(const MaskedArgs& a, int t, uint32_t lane)
-    {
-        return FlaggedBlock{row_rsrc(a.Y + (int64_t)t * a.ld), row_rsrc(a.valid + (int64_t)t * a.ldv),
-                            (uint32_t)a.ld * 4u, (uint32_t)a.ldv, lane};
-    }
-};
-
-// LDS is what limits residency (one ring slot per window position and lane),
-// so the kernel may use up to 256 VGPRs without losing waves.
-template <int K, int F, bool EXPORT, bool EXPLICIT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void
-masked_periodic_kernel(MaskedArgs a)
-{
-    using Gk = Gram<K>;
-    using Cur = CursorOf<EXPLICIT>;
-    using V = typename Cur::type::value_type;
-    constexpr int NP = Gk::NP, NG = Gk::NG, NL = Gk::NL;
-    constexpr int NT = 4 * K;  // phase-table row: sin, cos of m w (t+1), m = 1..2k
-    // Window ring, cap slots x kBlock lanes of 6 bytes: a 32-bit high word and a
-    // 16-bit middle word.  History slots hold (y_t as float bits, t); monitoring
-    // slots hold a residual kept to 36 mantissa bits (the low 16 bits cleared
-    // before it enters the MOSUM, so it leaves the sum exactly as it entered).
-    extern __shared__ uint32_t ring_hi[];
-    const int tid = threadIdx.x;
-    const int64_t pix = (int64_t)blockIdx.x * kBlock + tid;
-    const bool active = pix < a.P;
-    const uint32_t lane = (uint32_t)(active ? pix : a.P - 1);
-    const int n = a.n, N = a.N;
-    const int cap = ring_slots(a.cap);  // the longest window: rows are written only when observed
-    const ctab ph = as_const(a.ph);
-    uint32_t* const rhi = ring_hi + tid;
-    uint16_t* const rmid = reinterpret_cast<uint16_t*>(ring_hi + cap * kBlock) + tid;
-    const double c0 = 0.5 * (double)(n - 1);  // tau_t = (t - c0) / n for 0-based t
-
-    // ---- history rows: per-phase counts and sums ----
-    uint32_t acc[F];
-    double A[F];
-#pragma unroll
-    for (int r = 0; r < F; ++r) {
-        acc[r] = 0u;
-        A[r] = 0.0;
-    }
-    double yy = 0.0, Bd = 0.0;
-    uint32_t cnt = 0u, zs = 0u, ymaxb = 0u;
-    bool bad = false;
-    int wp = 0;  // next ring slot
-    uint32_t inc = 1u;
-    double bd = 0.0;
-    // Centring constant c: the first observed history value, found in the first
-    // block as it arrives; only a wave with a lane that has nothing observed
-    // there scans further blocks.
-    float cf = 0.0f;
-    double c = 0.0;
-    auto first_observed = [&](const V* buf, int t0, bool have) {
-        const int lim = n - 1 - t0;
-        float first = 0.0f;
-        bool any = false;
-#pragma unroll
-        for (int u = F - 1; u >= 0; --u) {
-            const bool ok = u <= lim && observed(buf[u]);
-            first = ok ? value(buf[u]) : first;
-            any = any || ok;
-        }
-        cf = have ? cf : first;
-        return have || any;
-    };
-    auto init = [&](const V* buf) {
-        bool have = first_observed(buf, 0, false);
-        for (int t0 = F; t0 < n && !__all(have); t0 += F) {
-            const typename Cur::type cc = Cur::at(a, t0, lane);
-            const int lim = n - 1 - t0;
-            V more[F];
-#pragma unroll
-            for (int u = 0; u < F; ++u) more[u] = cc.load(u < lim ? u : lim);
-            have = first_observed(more, t0, have);
-        }
-        c = (double)cf;
-    };
-    stream_blocks<F>(
-        [&](int t) { return Cur::at(a, t, lane); }, 0, n,
-        [&](int u, int t, V val, bool in) {
-            const bool ok = in && observed(val);
-            const float v = value(val);
-            if (EXPLICIT) bad = bad || (ok && !isfinite(v));
-            // Lanes whose row is missing sit this one out (execution mask, no selects).
-            if (ok) {
-                const double d = (double)v - c;
-                A[u] += d;
-                yy = fma(d, d, yy);
-                Bd = fma(bd, d, Bd);
-                acc[u] += inc;
-                ++cnt;
-                ymaxb = max(ymaxb, __float_as_uint(v) & 0x7fffffffu);
-                rhi[wp * kBlock] = __float_as_uint(v);
-                rmid[wp * kBlock] = (uint16_t)t;
-                wp = wp + 1 == cap ? 0 : wp + 1;
-            }
-        },
-        [&](int tb) {
-            const uint32_t b = (uint32_t)(tb / F);
-            // sum over observed rows of b^2 by parts: (B-1)^2 n_v - sum_b (2b-1) C_b,
-            // C_b the count before block b.
-            if (b > 0) zs += (2u * b - 1u) * cnt;
-            inc = 1u + (b << kCountBits);
-            bd = (double)b;
-        },
-        init);
-
-    // ---- Gram matrix and right-hand side from the phase sums (Eq. 5-6) ----
-    const int nv = (int)cnt;
-    const uint32_t blast = (uint32_t)((n - 1) / F);
-    const uint32_t zsum = blast * blast * cnt - zs;  // sum w_t b_t^2 (exact below 2^32)
-    double gs[NG], bq[NP];
-#pragma unroll
-    for (int i = 0; i < NG; ++i) gs[i] = 0.0;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) bq[j] = 0.0;
-    double s_t = 0.0, s_tt = 0.0, s_rA = 0.0;
-#pragma unroll
-    for (int r = 0; r < F; ++r) {
-        const double w = (double)(acc[r] & kCountMask);
-        const double q = (double)(acc[r] >> kCountBits);
-        const double rc = (double)r - c0;
-        const double U = fma(rc, w, (double)F * q);  // sum over phase r of w (t - c0)
-        s_t += U;
-        s_tt = fma(rc * rc, w, fma(2.0 * F * rc, q, s_tt));
-        bq[0] += A[r];
-        s_rA = fma(rc, A[r], s_rA);
-#pragma unroll
-        for (int m = 1; m <= 2 * K; ++m) {
-            gs[1 + m] = fma(w, ph[r * NT + 2 * (m - 1)], gs[1 + m]);
-            gs[1 + 2 * K + m] = fma(w, ph[r * NT + 2 * (m - 1) + 1], gs[1 + 2 * K + m]);
-        }
-#pragma unroll
-        for (int j = 1; j <= K; ++j) {
-            const double sj = ph[r * NT + 2 * (j - 1)], cj = ph[r * NT + 2 * (j - 1) + 1];
-            gs[1 + 4 * K + j] = fma(U, sj, gs[1 + 4 * K + j]);
-            gs[1 + 5 * K + j] = fma(U, cj, gs[1 + 5 * K + j]);
-            bq[2 * j] = fma(A[r], sj, bq[2 * j]);
-            bq[2 * j + 1] = fma(A[r], cj, bq[2 * j + 1]);
-        }
-    }
-    const double inv_n = 1.0 / (double)n;
-    s_tt = fma((double)F * (double)F, (double)zsum, s_tt);
-    gs[0] = s_t * inv_n;
-    gs[1] = s_tt * (inv_n * inv_n);
-#pragma unroll
-    for (int j = 1; j <= K; ++j) {
-        gs[1 + 4 * K + j] *= inv_n;
-        gs[1 + 5 * K + j] *= inv_n;
-    }
-    bq[1] = fma((double)F, Bd, s_rA) * inv_n;
-
-    // ---- fit on the observed history ----
-    const int H = a.h_window > 0 ? a.h_window : (int)floor(a.h_frac * (double)nv);
-    uint8_t st = BFM_ST_OK;
-    if (bad)
-        st = BFM_ST_NONFINITE;
-    else if (nv <= NP || H < 1 || H > nv)
-        st = BFM_ST_INSUFFICIENT;
-    double L[NL];
-    Gk::assemble(gs, (double)nv, L);
-    const double tol = kRankTol * sqrt((double)nv);
-    const bool full_rank = Gk::cholesky(L, tol * tol);
-    if (st == BFM_ST_OK && !full_rank) st = BFM_ST_RANK_DEFICIENT;
-    const bool fitted = st == BFM_ST_OK;  // beta and sigma are defined
-    double z[NP], beta[NP];
-    double zz = 0.0;
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-        double s = bq[i];
-#pragma unroll
-        for (int k = 0; k < i; ++k) s = fma(-L[tri(i, k)], z[k], s);
-        z[i] = s / L[tri(i, i)];
-        zz = fma(z[i], z[i], zz);
-    }
-#pragma unroll
-    for (int i = NP - 1; i >= 0; --i) {
-        double s = z[i];
-#pragma unroll
-        for (int k = i + 1; k < NP; ++k) s = fma(-L[tri(k, i)], beta[k], s);
-        beta[i] = s / L[tri(i, i)];
-    }
-    const double sig = sqrt(fmax(yy - zz, 0.0) / (double)(nv - NP));
-    const double scale = sig * sqrt((double)nv);
-    if (st == BFM_ST_OK && sig <= kSigmaRelTol * (double)__uint_as_float(ymaxb))
-        st = BFM_ST_DEGENERATE_SIGMA;
-    const bool monitor = st == BFM_ST_OK;
-
-    // Fitted value at row t = F b + r: P_r + gamma b (the centring constant included).
-    double Pw[F];
-#pragma unroll
-    for (int r = 0; r < F; ++r) {
-        double v = fma(beta[1], ((double)r - c0) * inv_n, beta[0] + c);
-#pragma unroll
-        for (int j = 1; j <= K; ++j) {
-            v = fma(beta[2 * j], ph[r * NT + 2 * (j - 1)], v);
-            v = fma(beta[2 * j + 1], ph[r * NT + 2 * (j - 1) + 1], v);
-        }
-        Pw[r] = v;
-    }
-    const double gamma = beta[1] * (double)F * inv_n;
-
-    // ---- outputs of the fit, written before the monitoring loop ----
-    const double qnan = __builtin_nan("");
-    if (active && a.beta) {
-        // beta~ is in the centred-trend basis of the centred series; map it to
-        // the basis of Eq. 2: tau = (t - (n+1)/2)/n with t the 1-based time.
-        const bool have_fit = fitted && !bad;
-        const double tc = 0.5 * (double)(n + 1);
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-            double v = beta[j];
-            if (j == 0) v = beta[0] - (tc / (double)n) * beta[1] + c;
-            if (j == 1) v = beta[1] / (double)n;
-            put_out(a.beta, (int64_t)j * a.P + pix, have_fit ? v : qnan, a.out_f64);
-        }
-    }
-
-    // ---- the last H observed history values become residuals ----
-    // Four slots per step, so that their phase-table gathers are in flight
-    // together; the wave stops at its largest window.
-    double S = 0.0;
-    int hmax = monitor ? H : 0;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) hmax = max(hmax, __shfl_xor(hmax, o));
-    hmax = __builtin_amdgcn_readfirstlane(hmax);
-    for (int i0 = 0; i0 < hmax; i0 += 4) {
-        int slot[4], t[4];
-        float y[4];
-        double hr[4][2 * K + 1];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {  // slots past the lane's window read slot 0, unused
-            slot[k] = wp - H + i0 + k;
-            slot[k] += slot[k] < 0 ? cap : 0;
-            slot[k] = monitor && i0 + k < H ? slot[k] : 0;
-            y[k] = __uint_as_float(rhi[slot[k] * kBlock]);
-            t[k] = rmid[slot[k] * kBlock];
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const double* row = a.ph + (t[k] % F) * NT;
-#pragma unroll
-            for (int j = 0; j < 2 * K; ++j) hr[k][j] = row[j];
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (monitor && i0 + k < H) {
-                double pr = fma(beta[1], ((double)t[k] - c0) * inv_n, beta[0] + c);
-#pragma unroll
-                for (int j = 1; j <= K; ++j) {
-                    pr = fma(beta[2 * j], hr[k][2 * (j - 1)], pr);
-                    pr = fma(beta[2 * j + 1], hr[k][2 * (j - 1) + 1], pr);
-                }
-                S += ring_store(rhi, rmid, slot[k], (double)y[k] - pr);
-            }
-        }
-    }
-
-    // ---- monitoring period (Eq. 3 and Eq. 4 at compacted positions) ----
-    int rp = wp - H;  // slot of the residual that leaves the window next
-    rp += rp < 0 ? cap : 0;
-    const double thr_flat = a.lambda * scale;
-    const double thr2 = thr_flat * thr_flat;
-    const float l2nv = __log2f((float)nv);
-    // Largest compacted count m with m / n_v <= e: up to there log+ is 1.
-    int ue = (int)floor(M_E * (double)nv);
-    while (ue > 0 && (double)ue / (double)nv > M_E) --ue;
-    while ((double)(ue + 1) / (double)nv <= M_E) ++ue;
-    // Rows before t_split cannot take any lane of the wave past ue (one
-    // observation per row at most): the boundary there is lambda.
-    int room = monitor ? ue - nv : INT_MAX;  // lanes that do not monitor do not count
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) room = min(room, __shfl_xor(room, o));
-    room = __builtin_amdgcn_readfirstlane(room);  // the same in every lane: keep it scalar
-    const int t_split = room >= N - n ? N : n + (room > 0 ? room : 0);
-    int u1 = nv;  // compacted (1-based) position of the latest observation
-    double hi = -INFINITY, lo = INFINITY;
-    int brk = INT_MAX;
-    double Gb = 0.0;
-    const double rscale = 1.0 / scale;
-    auto pre = [&](int tb) { Gb = gamma * (double)(tb / F); };
-    // The residual leaving the window is read one observation ahead (after the
-    // previous write, so the window still holds exactly the last H residuals):
-    // its LDS latency overlaps the rest of the row.
-    uint32_t old_hi = rhi[rp * kBlock];
-    uint16_t old_mid = rmid[rp * kBlock];
-    stream_blocks<F>(
-        [&](int t) { return Cur::at(a, t, lane); }, n, N,
-        [&](int u, int t, V val, bool in) {
-            const bool ok = in && observed(val);
-            const float v = value(val);
-            if (EXPLICIT) bad = bad || (ok && !isfinite(v));
-            if (ok) {  // lanes whose row is missing sit this one out
-                const double r = ring_store(rhi, rmid, wp, (double)v - (Pw[u] + Gb));
-                S += r - ring_value(old_hi, old_mid);
-                wp = wp + 1 == cap ? 0 : wp + 1;
-                rp = rp + 1 == cap ? 0 : rp + 1;
-                old_hi = rhi[rp * kBlock];
-                old_mid = rmid[rp * kBlock];
-                hi = max_num(hi, S);
-                lo = min_num(lo, S);
-                ++u1;
-                bool cross = fabs(S) > thr_flat;
-                if (t >= t_split)  // wave-uniform; not reached while every u/n_v stays below e
-                    cross = cross_past_e(cross, S, thr2, u1, ue, nv, l2nv);
-                brk = cross ? min(brk, t - n) : brk;
-            }
-            if (EXPORT && a.mosum && active && in)
-                put_out(a.mosum, (int64_t)(t - n) * a.P + lane, monitor && ok ? S * rscale : qnan,
-                        a.out_f64);
-        },
-        pre, [](const V*) {});
-
-    if (bad) st = BFM_ST_NONFINITE;
-    if (st == BFM_ST_OK && u1 == nv) st = BFM_ST_NO_MONITOR;
-    if (!active) return;
-
-    const bool have_fit = fitted && st != BFM_ST_NONFINITE;
-    double mag = qnan;
-    if (st == BFM_ST_OK) mag = (hi >= -lo ? hi : lo) * rscale;
-    if (st != BFM_ST_OK || brk == INT_MAX) brk = -1;
-    a.brk[pix] = brk;
-    if (a.mag) put_out(a.mag, pix, mag, a.out_f64);
-    if (a.status) a.status[pix] = st;
-    if (a.sigma) put_out(a.sigma, pix, have_fit ? sig : qnan, a.out_f64);
-    if (EXPORT) {
-        if (a.resid) {
-            for (int tb = 0; tb < N; tb += F) {
-                const double g = gamma * (double)(tb / F);
-#pragma unroll
-                for (int u = 0; u < F; ++u) {
-                    const int t = tb + u;
-                    if (t < N) {
-                        const float v = a.Y[(int64_t)t * a.ld + pix];
-                        const bool ok = EXPLICIT ? a.valid[(int64_t)t * a.ldv + pix] != 0 : isfinite(v);
-                        const double r = have_fit && ok ? (double)v - (Pw[u] + g) : qnan;
-                        put_out(a.resid, (int64_t)t * a.P + pix, r, a.out_f64);
-                    }
-                }
-            }
-        }
-        if (a.mosum && st != BFM_ST_OK)
-            for (int m = 0; m < N - n; ++m) put_out(a.mosum, (int64_t)m * a.P + pix, qnan, a.out_f64);
-    }
-}
-
-template <int K, int F, bool EXPLICIT>
-hipError_t launch_kf(const MaskedArgs& a, hipStream_t stream)
-{
-    const dim3 grid((unsigned)((a.P + kBlock - 1) / kBlock));
-    const size_t lds = masked_periodic_lds_bytes(a.cap);
-    if (a.n >= 65536) return hipErrorInvalidValue;  // history rows are kept as 16-bit indices
-    if (a.resid || a.mosum)
-        hipLaunchKernelGGL((masked_periodic_kernel<K, F, true, EXPLICIT>), grid, dim3(kBlock), lds,
-                           stream, a);
-    else
-        hipLaunchKernelGGL((masked_periodic_kernel<K, F, false, EXPLICIT>), grid, dim3(kBlock), lds,
-                           stream, a);
-    return hipGetLastError();
-}
-
-template <int K, bool EXPLICIT>
-hipError_t launch_k(const MaskedArgs& a, hipStream_t stream)
-{
-    switch (a.F) {
-    case 12: return launch_kf<K, 12, EXPLICIT>(a, stream);
-    case 23: return launch_kf<K, 23, EXPLICIT>(a, stream);
-    case 24: return launch_kf<K, 24, EXPLICIT>(a, stream);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <bool EXPLICIT>
-hipError_t launch_mode(const MaskedArgs& a, int order, hipStream_t stream)
-{
-    switch (order) {
-    case 0: return launch_k<0, EXPLICIT>(a, stream);
-    case 1: return launch_k<1, EXPLICIT>(a, stream);
-    case 2: return launch_k<2, EXPLICIT>(a, stream);
-    case 3: return launch_k<3, EXPLICIT>(a, stream);
-    case 4: return launch_k<4, EXPLICIT>(a, stream);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-}  // namespace
 
 size_t masked_periodic_lds_bytes(int cap) { return (size_t)ring_slots(cap) * kBlock * 6; }
 
 hipError_t launch_masked_periodic(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream)
 {
-    return mask_mode == BFM_MASK_EXPLICIT ? launch_mode<true>(a, order, stream)
-                                          : launch_mode<false>(a, order, stream);
+    if (a.y_dtype != BFM_Y_F32) return launch_masked_periodic_16(a, order, mask_mode, stream);
+    return launch_t<float>(a, order, mask_mode, stream);
 }
 
 }  // namespace bfm

@@ -1,0 +1,291 @@
+// Period-blocked plain-path kernel of BFAST Monitor for gfx950 (FP64
+// arithmetic), used when the number of observations per year f is an integer
+// F (12, 23, 24).  The harmonic regressors of Eq. 2 then repeat every F rows,
+// which removes every per-row table read from the streaming loops:
+//
+//   history  d_t = y_t - c;  A[t mod F] += d_t;  Tr += (t+1) d_t;  yy += d_t^2.
+//            Afterwards g = X~_n' d follows from the F phase sums (harmonics
+//            at each phase from a small table) and Tr (trend), b' = R^-T g
+//            (coordinates in the orthonormal basis of Section 3's shared
+//            operator), RSS = yy - ||b'||^2, beta~ = R^-1 b'.
+//   monitor  the window sum of fitted values (Eq. 3) is
+//            Lc + gamma (t+1) + Pw[t mod F]: a linear trend part and a per-phase
+//            part, both computed once per pixel.  S'_t = S'_{t-1} + y_t -
+//            y_{t-H} - gamma (window sum of observations minus the trend part;
+//            y_{t-H} from the per-lane LDS ring) and num_t = S'_t - Pw[t mod F]
+//            is the window sum of residuals, tested against b_t sigma sqrt(n).
+//
+// Rows are processed in blocks aligned to multiples of F so that a row's phase
+// is a compile-time register index.  The series may be stored as float32, BF16
+// or FP16 (template parameter T); arithmetic is FP64 either way.
+//
+// This header holds the kernel template; periodic_kernel.hip (float32) and
+// periodic_kernel_16.hip (BF16, FP16) instantiate it.
+#pragma once
+
+#include <climits>
+#include <cmath>
+
+#include "bfm_internal.hpp"
+#include "device_common.hpp"
+
+namespace bfm {
+namespace {
+
+using namespace dev;
+
+template <int K, int F, bool EXPORT, typename T>
+#ifndef BFM_PERIODIC_OCC
+// Three waves per SIMD: the LDS ring of a 50-row window allows twelve per CU.
+#define BFM_PERIODIC_OCC __attribute__((amdgpu_waves_per_eu(3)))
+#endif
+__global__ __launch_bounds__(kPlainBlock) BFM_PERIODIC_OCC
+void periodic_kernel(PeriodicArgs a)
+{
+    constexpr int NP = 2 + 2 * K;
+    constexpr int NH = 2 * K;
+    extern __shared__ float ring[];  // H rows x kPlainBlock lanes
+    const int tid = threadIdx.x;
+    const int64_t pix = (int64_t)blockIdx.x * kPlainBlock + tid;
+    const bool active = pix < a.P;
+    const uint32_t lane = (uint32_t)(active ? pix : a.P - 1);
+    const uint32_t lane_bytes = lane * (uint32_t)sizeof(T);
+    const int n = a.n, N = a.N, H = a.H;
+    const int64_t ld = a.ld;
+    const T* __restrict__ Y = static_cast<const T*>(a.Y);
+    const ctab rt = as_const(a.tab);
+    const ctab ri = rt + NP * NP;
+    const ctab hh = ri + NP * NP;
+    const ctab wh = hh + F * NH;
+    const ctab bnd = wh + F * NH;
+    float* const myring = ring + tid;
+
+    // ---- history (Eq. 5-6) ----
+    const double c = (double)load_obs(Y, lane_bytes);
+    double A[F];
+#pragma unroll
+    for (int u = 0; u < F; ++u) A[u] = 0.0;
+    double yy = 0.0;
+    // Trend sum Tr = sum_t (t+1) d_t, with t + 1 = F b + u + 1 for row u of block
+    // b: Tr = F sum_b b (block sum) + sum_u (u+1) A[u]; Wb = sum_t b d_t needs one
+    // FMA per row against the block index held in a register.
+    double Wb = 0.0, bidx = 0.0;
+    // max |y| over the history as an unsigned maximum of the magnitude bits
+    // (their order is the order of the magnitudes; NaN pixels are flagged anyway).
+    uint32_t ymax_bits = 0;
+    auto hist = [&](int u, int t, float v) {
+        const double d = (double)v - c;
+        yy = fma(d, d, yy);
+        A[u] += d;
+        Wb = fma(bidx, d, Wb);
+        ymax_bits = max(ymax_bits, __float_as_uint(v) & 0x7fffffffu);
+        (void)t;
+    };
+    auto hist_pre = [&](int tb, int, int) { bidx = (double)(tb / F); };
+    // Rows from a block boundary at or before n - H also go to the ring, so that
+    // it holds the last H history rows when the history ends.
+    const int B = ((n - H) / F) * F;
+    stream_aligned<F>(ObsCursorT<T>{Y, ld, lane_bytes}, 0, B, hist, hist_pre);
+    int slot = B % H;  // ring slot of the next row: t mod H
+    stream_aligned<F>(
+        ObsCursorT<T>{Y + (int64_t)B * ld, ld, lane_bytes}, B, n,
+        [&](int u, int t, float v) {
+            hist(u, t, v);
+            myring[slot * kPlainBlock] = v;
+            slot = slot + 1 == H ? 0 : slot + 1;
+        },
+        hist_pre);
+
+    // ---- fit: g = X~_n' d from the phase sums, b' = R^-T g ----
+    double g[NP];
+    double g0 = 0.0;
+#pragma unroll
+    for (int u = 0; u < F; ++u) g0 += A[u];
+    double Tr = (double)F * Wb;
+#pragma unroll
+    for (int u = 0; u < F; ++u) Tr = fma((double)(u + 1), A[u], Tr);
+    g[0] = g0;
+    g[1] = (Tr - 0.5 * (double)(n + 1) * g0) / (double)n;
+#pragma unroll
+    for (int j = 0; j < NH; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < F; ++u) s = fma(hh[u * NH + j], A[u], s);
+        g[2 + j] = s;
+    }
+    double bq[NP], beta[NP];
+    double rss = yy;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k <= i; ++k) s = fma(rt[i * NP + k], g[k], s);
+        bq[i] = s;
+        rss = fma(-s, s, rss);
+    }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = i; k < NP; ++k) s = fma(ri[i * NP + k], bq[k], s);
+        beta[i] = s;
+    }
+    const double sig = sqrt(fmax(rss, 0.0) * a.inv_dof);
+    const double scale = sig * a.sqrt_n;
+    const double tc = 0.5 * (double)(n + 1);
+    const double qnan = __builtin_nan("");
+    const bool hist_bad = !isfinite(yy);
+    const bool degenerate = sig <= kSigmaRelTol * (double)__uint_as_float(ymax_bits);
+    // The fit's outputs are written now, so that the coefficients need not stay
+    // live through the monitoring loop; a non-finite monitoring value found later
+    // turns them into NaN.
+    auto write_fit = [&](bool bad) {
+        if (a.sigma) put_out(a.sigma, pix, bad ? qnan : sig, a.out_f64);
+        if (a.beta) {
+            // beta~ is in the centred-trend basis of the centred series; map it
+            // to the basis of Eq. 2: tau = (t - (n+1)/2)/n.
+            for (int j = 0; j < NP; ++j) {
+                double v = beta[j];
+                if (j == 0) v = beta[0] - (tc / (double)n) * beta[1] + c;
+                if (j == 1) v = beta[1] / (double)n;
+                put_out(a.beta, (int64_t)j * a.P + pix, bad ? qnan : v, a.out_f64);
+            }
+        }
+    };
+    if (active) write_fit(hist_bad);
+
+    // ---- window sums of fitted values: Lc + gamma (t+1) + Pw[t mod F] ----
+    double Pw[F];
+#pragma unroll
+    for (int u = 0; u < F; ++u) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < NH; ++j) s = fma(wh[u * NH + j], beta[2 + j], s);
+        Pw[u] = s;
+    }
+    const double Hd = (double)H;
+    const double gamma = beta[1] * Hd / (double)n;
+    const double Lc = Hd * beta[0] - beta[1] * Hd * (0.5 * (Hd - 1.0) + tc) / (double)n;
+
+    // Window sum over the last H history rows (all ring slots), minus the trend
+    // part at t = n - 1.
+    double S = 0.0;
+    for (int s = 0; s < H; ++s) S += (double)myring[s * kPlainBlock] - c;
+    double Sp = S - Lc - gamma * (double)n;
+
+    // ---- monitoring period (Eq. 3, Eq. 4) ----
+    double hi = -INFINITY, lo = INFINITY;
+    int brk = INT_MAX;  // rows ascend, so the first crossing is the smallest m
+    float vo[F];
+    int s0 = slot;
+    // The window is at least F rows long, so a block's ring reads precede its
+    // writes and can be issued together.
+    auto pre = [&](int, int lo_, int hi_) {
+        s0 = slot;
+#pragma unroll
+        for (int u = 0; u < F; ++u) {
+            if (u >= lo_ && u < hi_) {
+                int s = s0 + (u - lo_);
+                s -= s >= H ? H : 0;
+                vo[u] = myring[s * kPlainBlock];
+            }
+        }
+        slot = s0 + (hi_ - lo_);
+        slot -= slot >= H ? H : 0;
+    };
+    // Ring writes: row t goes to slot t mod H.  Within a block, the first row
+    // handed over has slot s0 and the rows follow in order.
+    int wslot = 0;
+    auto pre_w = [&](int tb, int lo_, int hi_) {
+        pre(tb, lo_, hi_);
+        wslot = s0;
+    };
+    auto row = [&](int u, int t, float v, double thr) {
+        myring[wslot * kPlainBlock] = v;
+        wslot = wslot + 1 == H ? 0 : wslot + 1;
+        Sp += ((double)v - (double)vo[u]) - gamma;
+        const double num = Sp - Pw[u];
+        const int m = t - n;
+        brk = fabs(num) > thr ? min(brk, m) : brk;
+        hi = fmax(hi, num);
+        lo = fmin(lo, num);
+        if (EXPORT && a.mosum && active)
+            put_out(a.mosum, (int64_t)m * a.P + lane, num / scale, a.out_f64);
+    };
+    // Eq. 4 is flat (b_t = lambda) while t/n <= e; blocks entirely in that part
+    // use one threshold, the rest read b_t per row.
+    const int t_flat = n + a.m_flat;
+    const int tA = t_flat >= N ? N : (t_flat / F) * F > n ? (t_flat / F) * F : n;
+    const double thr_flat = a.lambda * scale;
+    stream_aligned<F>(ObsCursorT<T>{Y + (int64_t)n * ld, ld, lane_bytes}, n, tA,
+                      [&](int u, int t, float v) { row(u, t, v, thr_flat); }, pre_w);
+    stream_aligned<F>(ObsCursorT<T>{Y + (int64_t)tA * ld, ld, lane_bytes}, tA, N,
+                      [&](int u, int t, float v) { row(u, t, v, bnd[t - n] * scale); }, pre_w);
+
+    const bool bad = hist_bad || !isfinite(Sp);
+    const uint8_t st = bad ? BFM_ST_NONFINITE : degenerate ? BFM_ST_DEGENERATE_SIGMA : BFM_ST_OK;
+    if (!active) return;
+
+    double mag = qnan;
+    if (st == BFM_ST_OK) mag = (hi >= -lo ? hi : lo) / scale;
+    if (st != BFM_ST_OK || brk == INT_MAX) brk = -1;
+    a.brk[pix] = brk;
+    if (a.mag) put_out(a.mag, pix, mag, a.out_f64);
+    if (a.status) a.status[pix] = st;
+    if (bad && !hist_bad) write_fit(true);
+    if (EXPORT) {
+        if (a.resid) {
+            for (int t = 0; t < N; ++t) {
+                double r = qnan;
+                if (st != BFM_ST_NONFINITE) {
+                    const int ph = t % F;
+                    r = (double)to_float(Y[(int64_t)t * ld + pix]) - c - beta[0] -
+                        beta[1] * ((double)(t + 1) - tc) / (double)n;
+                    for (int j = 0; j < NH; ++j) r = fma(-hh[ph * NH + j], beta[2 + j], r);
+                }
+                put_out(a.resid, (int64_t)t * a.P + pix, r, a.out_f64);
+            }
+        }
+        if (a.mosum && st != BFM_ST_OK)
+            for (int m = 0; m < N - n; ++m) put_out(a.mosum, (int64_t)m * a.P + pix, qnan, a.out_f64);
+    }
+}
+
+template <int K, int F, typename T>
+hipError_t launch_kf(const PeriodicArgs& a, hipStream_t stream)
+{
+    const dim3 grid((unsigned)((a.P + kPlainBlock - 1) / kPlainBlock));
+    const size_t lds = (size_t)a.H * kPlainBlock * sizeof(float);
+    if (a.resid || a.mosum)
+        hipLaunchKernelGGL((periodic_kernel<K, F, true, T>), grid, dim3(kPlainBlock), lds, stream, a);
+    else
+        hipLaunchKernelGGL((periodic_kernel<K, F, false, T>), grid, dim3(kPlainBlock), lds, stream, a);
+    return hipGetLastError();
+}
+
+template <int F, typename T>
+hipError_t launch_f(const PeriodicArgs& a, int order, hipStream_t stream)
+{
+    switch (order) {
+    case 0: return launch_kf<0, F, T>(a, stream);
+    case 1: return launch_kf<1, F, T>(a, stream);
+    case 2: return launch_kf<2, F, T>(a, stream);
+    case 3: return launch_kf<3, F, T>(a, stream);
+    case 4: return launch_kf<4, F, T>(a, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_t(const PeriodicArgs& a, int order, int F, hipStream_t stream)
+{
+    switch (F) {
+    case 12: return launch_f<12, T>(a, order, stream);
+    case 23: return launch_f<23, T>(a, order, stream);
+    case 24: return launch_f<24, T>(a, order, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+}  // namespace bfm

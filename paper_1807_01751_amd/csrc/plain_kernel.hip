@@ -197,7 +197,8 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
 }
 
 // Pixels whose parameters leave nothing to fit.
-__global__ __launch_bounds__(256) void fill_status_kernel(const float* __restrict__ Y, int64_t ld,
+template <typename T>
+__global__ __launch_bounds__(256) void fill_status_kernel(const T* __restrict__ Y, int64_t ld,
                                                           int64_t P, int N, int n, int p,
                                                           uint8_t st0, bfm_outputs out,
                                                           int mask_mode,
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(256) void fill_status_kernel(const float* __restric
     if (mask_mode != BFM_MASK_NAN)
         for (int t = 0; t < N; ++t) {
             bool used = mask_mode == BFM_MASK_NONE || valid[(int64_t)t * ldv + pix] != 0;
-            bad |= used && !isfinite(Y[(int64_t)t * ld + pix]);
+            bad |= used && !isfinite(to_float(Y[(int64_t)t * ld + pix]));
         }
     const uint8_t st = bad ? (uint8_t)BFM_ST_NONFINITE : st0;
     const double qnan = __builtin_nan("");
@@ -258,13 +259,20 @@ hipError_t launch_plain(const PlainArgs& a, int p, hipStream_t stream)
     }
 }
 
-hipError_t launch_fill_status(const float* Y, int64_t ld, int64_t P, int N, int n, int p,
+hipError_t launch_fill_status(const void* Y, int y_dtype, int64_t ld, int64_t P, int N, int n, int p,
                               uint8_t st, const bfm_outputs& out, int mask_mode,
                               const uint8_t* valid, int64_t ldv, hipStream_t stream)
 {
     const dim3 grid((unsigned)((P + 255) / 256));
-    hipLaunchKernelGGL(fill_status_kernel, grid, dim3(256), 0, stream, Y, ld, P, N, n, p, st, out,
-                       mask_mode, valid, ldv);
+    if (y_dtype == BFM_Y_BF16)
+        hipLaunchKernelGGL(fill_status_kernel<bf16_t>, grid, dim3(256), 0, stream,
+                           static_cast<const bf16_t*>(Y), ld, P, N, n, p, st, out, mask_mode, valid, ldv);
+    else if (y_dtype == BFM_Y_F16)
+        hipLaunchKernelGGL(fill_status_kernel<f16_t>, grid, dim3(256), 0, stream,
+                           static_cast<const f16_t*>(Y), ld, P, N, n, p, st, out, mask_mode, valid, ldv);
+    else
+        hipLaunchKernelGGL(fill_status_kernel<float>, grid, dim3(256), 0, stream,
+                           static_cast<const float*>(Y), ld, P, N, n, p, st, out, mask_mode, valid, ldv);
     return hipGetLastError();
 }
 

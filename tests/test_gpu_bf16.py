@@ -1,0 +1,168 @@
+"""GPU parity of series stored in 16 bits (bfm_fit_monitor_typed with BFM_Y_BF16
+or BFM_Y_F16).
+
+A 16-bit observation decodes exactly to a float32, and the arithmetic stays
+FP64, so the bar is the FP64 one against the oracle run on the decoded series.
+A second check reports how far the narrower storage moves the results from those
+on the original float32 series (an accuracy statement, not a parity bar).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from parity import compare, to_numpy
+
+pytestmark = pytest.mark.gpu
+
+ALL = ("brk", "mag", "sigma", "status", "beta", "resid", "mosum")
+
+
+@pytest.fixture(scope="module")
+def bfm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1807_01751_amd import bfm as b
+    b.load()
+    return b
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bnd_of(N, n, lam):
+    t = np.arange(n + 1, N + 1) / n
+    return lam * np.sqrt(np.where(t <= np.e, 1.0, np.log(np.maximum(t, 1.0))))
+
+
+def series(P, N, n, order=3, seed=0, freq=23.0, miss=0.0):
+    from paper_1807_01751_amd.synth import apply_missing, make_missing, make_series, split_rate
+    Y, _ = make_series(P, N, n, max(order, 1), freq=freq, seed=seed, device="cuda")
+    if miss > 0:
+        r = split_rate(miss)
+        Y = apply_missing(Y, make_missing(N, P, iid=r, runs=r, seed=seed + 100, device="cuda"))
+    return Y
+
+
+def decoded(Yb):
+    """The float32 values a 16-bit tensor stores (exact)."""
+    return Yb.float().cpu().numpy()
+
+
+NARROW = pytest.mark.parametrize("dt", [torch.bfloat16, torch.float16], ids=["bf16", "f16"])
+
+
+@NARROW
+@pytest.mark.parametrize("freq,order,N,n", [(23.0, 3, 228, 114), (12.0, 2, 150, 72),
+                                            (24.0, 4, 400, 100)])
+def test_bf16_plain_parity(bfm, orc, freq, order, N, n, dt):
+    say(f"case {dt} plain f={freq} k={order} N={N} n={n} P=2000")
+    Yb = series(2000, N, n, order, seed=11 + order, freq=freq).to(dt)
+    g = to_numpy(bfm.fit_monitor(Yb, n=n, order=order, freq=freq, outputs=ALL))
+    o = orc.fit_monitor(decoded(Yb), n=n, order=order, freq=freq, threads=0)
+    rep = compare(g, o, bnd=bnd_of(N, n, 2.5))
+    say(rep)
+    assert rep["not_ok"] == 0
+
+
+@NARROW
+@pytest.mark.parametrize("mode", ["nan", "explicit"])
+def test_bf16_masked_parity(bfm, orc, mode, dt):
+    say(f"case {dt} masked {mode} P=1500 N=300 n=150")
+    from test_gpu_masked import check, hist_count
+    Y = series(1500, 300, 150, seed=21, miss=0.25)
+    Yb = Y.to(dt)
+    if mode == "nan":
+        g = to_numpy(bfm.fit_monitor(Yb, n=150, mask_mode=bfm.MASK_NAN, outputs=ALL))
+        o = orc.fit_monitor(decoded(Yb), n=150, mask_mode=orc.MASK_NAN, threads=0)
+        used = hist_count(Yb.float(), 150)
+    else:
+        valid = torch.isfinite(Y).to(torch.uint8)
+        Yg = torch.where(valid.bool(), Y, torch.full_like(Y, 7.0)).to(dt)
+        g = to_numpy(bfm.fit_monitor(Yg, n=150, mask_mode=bfm.MASK_EXPLICIT, valid=valid,
+                                     outputs=ALL))
+        o = orc.fit_monitor(decoded(Yg), n=150, mask_mode=orc.MASK_EXPLICIT,
+                            valid=valid.cpu().numpy(), threads=0)
+        used = hist_count(Yg.float(), 150, valid)
+    say(check(g, o, 2.5, used))
+
+
+@NARROW
+def test_bf16_lean_matches_export(bfm, dt):
+    say(f"case {dt} lean-vs-export P=3000 N=228")
+    Yb = series(3000, 228, 114, seed=31).to(dt)
+    for mode in (bfm.MASK_NONE, bfm.MASK_NAN):
+        a = to_numpy(bfm.fit_monitor(Yb, n=114, mask_mode=mode,
+                                     outputs=("brk", "mag", "sigma", "status")))
+        b = to_numpy(bfm.fit_monitor(Yb, n=114, mask_mode=mode, outputs=ALL))
+        for k in a:
+            np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+@NARROW
+def test_bf16_degenerate_history_fills_status(bfm, dt):
+    """A parameter set whose history design is rank deficient (f = 2, k = 1) goes
+    through the status-only kernel; non-finite values still mark their pixels."""
+    say(f"case {dt} rank-deficient P=100 N=60 n=30 f=2")
+    Yb = series(100, 60, 30, 1, seed=41).to(dt)
+    Yb[3, 5] = float("inf")
+    g = to_numpy(bfm.fit_monitor(Yb, n=30, order=1, freq=2.0, outputs=("brk", "status")))
+    assert (g["brk"] == -1).all()
+    assert g["status"][5] == 1 and (np.delete(g["status"], 5) == 3).all()
+
+
+def test_bf16_unsupported_paths(bfm):
+    Yb = series(64, 100, 50, seed=51).to(torch.bfloat16)
+    for kw in (dict(freq=22.5), dict(freq=23.0, h=0.2), dict(freq=23.0, order=5),
+               dict(freq=22.5, mask_mode=1)):
+        with pytest.raises(bfm.BfmError) as e:
+            bfm.fit_monitor(Yb, n=50, **kw)
+        assert e.value.code == bfm.E_UNSUPPORTED, kw
+
+
+def test_bf16_full_tile_sampled(bfm, orc):
+    """1024x1024 pixels, N=400, n=200, k=3 stored as BF16: sampled parity."""
+    say("case bf16 full tile P=1048576 N=400 n=200")
+    P, N, n = 1 << 20, 400, 200
+    Yb = series(P, N, n, seed=2).to(torch.bfloat16)
+    g = to_numpy(bfm.fit_monitor(Yb, n=n, outputs=("brk", "mag", "sigma", "status")))
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.r_[np.arange(64), np.arange(P - 64, P), rng.integers(0, P, 3000)])
+    Ys = Yb[:, torch.as_tensor(idx, device="cuda")].float().cpu().numpy()
+    o = orc.fit_monitor(Ys, n=n, threads=0)
+    gs = {k: v[idx] for k, v in g.items()}
+    diff = gs["brk"] != o["brk"]
+    assert diff.sum() <= 1, diff.sum()
+    keep = ~diff
+    rep = compare({k: v[keep] for k, v in gs.items()}, {k: v[..., keep] for k, v in o.items()})
+    say("bf16 full tile sample", rep)
+
+
+@pytest.mark.parametrize("dt,agree_min,mo_max", [(torch.bfloat16, 0.93, 1.5), (torch.float16, 0.99, 0.25)],
+                         ids=["bf16", "f16"])
+def test_narrow_storage_accuracy_against_float32_series(bfm, dt, agree_min, mo_max):
+    """What 16-bit storage costs: results on the rounded series against those on
+    the float32 series (same kernels, FP64 arithmetic), at y ~ 0.5-1.2 with noise
+    0.02.  BF16 rounds to 2^-8 relative: over a slowly varying signal the rounding
+    errors of a 50-row window add up coherently, so MOSUM values move by up to
+    about 0.9 and 5% of break indices change (the planted steps are still all
+    found).  FP16 rounds to 2^-11: eight times finer.  The bars below are what
+    was measured, with room."""
+    say(f"case {dt} accuracy P=65536 N=400 n=200")
+    from paper_1807_01751_amd.synth import make_series
+    P, N, n = 1 << 16, 400, 200
+    Y, truth = make_series(P, N, n, 3, seed=61, device="cuda")
+    a = to_numpy(bfm.fit_monitor(Y, n=n, outputs=("brk", "mag", "mosum")))
+    b = to_numpy(bfm.fit_monitor(Y.to(dt), n=n, outputs=("brk", "mag", "mosum")))
+    agree = (a["brk"] == b["brk"]).mean()
+    mo_err = np.abs(a["mosum"] - b["mosum"]).max()
+    has = truth["has_step"].cpu().numpy()
+    found_a = (a["brk"][has] >= 0).mean()
+    found_b = (b["brk"][has] >= 0).mean()
+    say(f"{dt} vs f32: break agreement {agree:.5f}, max |dMO| {mo_err:.3g}, "
+        f"steps found {found_a:.4f} (f32) {found_b:.4f} ({dt})")
+    assert agree > agree_min
+    assert found_b >= found_a - 2e-3
+    assert mo_err < mo_max
