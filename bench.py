@@ -10,7 +10,10 @@ timed region; one step is one bfm_fit_monitor call over the whole tile
 
 After the headline leg, the same tile with 25% of its observations missing
 (NaN: half independent, half cloud runs of 3-15 rows) is timed through the
-masked path (per-pixel Gram and Cholesky); it is reported under "masked".
+masked path (per-pixel Gram and Cholesky); it is reported under "masked".  The
+mixed-precision leg ("mixed") stores the tile in FP16 (half the bytes) with the
+same FP64 arithmetic, and reports how its break indices and magnitudes compare
+with the float32 leg.
 
 Prints one JSON line.  Run with --gpus 1 (the default); more GPUs are not
 supported by this benchmark.
@@ -35,11 +38,15 @@ MISSING = 0.25
 # period, so the period-blocked kernels are used), the rocprofv3 summaries kept
 # for each, and the workload each is timed on.
 LEGS = {
-    "plain": {"kernel": "::periodic_kernel<3, 23, false>(",
+    "plain": {"kernel": "::periodic_kernel<3, 23, false, float>(",
               "traffic": os.path.join(PROFILES, "traffic_plain_1024x1024_N400.json"),
               "trace_md": os.path.join(PROFILES, "plain_periodic_k3_f23_1024x1024_N400_kernel_trace.md"),
               "workload": "1024x1024 pixels, N=400"},
-    "masked": {"kernel": "::masked_periodic_kernel<3, 23, false, false>(",
+    "mixed": {"kernel": "::periodic_kernel<3, 23, false, bfm::dev::f16_t>(",
+              "traffic": os.path.join(PROFILES, "traffic_mixed_f16_1024x1024_N400.json"),
+              "trace_md": os.path.join(PROFILES, "mixed_periodic_f16_k3_f23_1024x1024_N400_kernel_trace.md"),
+              "workload": "1024x1024 pixels, N=400, FP16-stored", "y_bytes": 2},
+    "masked": {"kernel": "::masked_periodic_kernel<3, 23, false, false, float>(",
                "traffic": os.path.join(PROFILES, "traffic_masked_1024x1024_N400_nan25.json"),
                "trace_md": os.path.join(PROFILES,
                                         "masked_periodic_k3_f23_1024x1024_N400_nan25_kernel_trace.md"),
@@ -122,6 +129,7 @@ def summarize_profiles(d):
     os.makedirs(PROFILES, exist_ok=True)
     for leg, spec in LEGS.items():
         KERNEL = spec["kernel"]
+        P_ALG = (spec.get("y_bytes", 4) * N + 8) * P
         stats = [r for r in trace if KERNEL in r["Name"]]
         assert stats, f"{leg} kernel missing from the trace"
         st = stats[0]
@@ -151,7 +159,8 @@ def summarize_profiles(d):
             f.write("| kernel | calls | average ns | min ns | max ns |\n|---|---|---|---|---|\n")
             f.write(f"| {st['Name']} | {st['Calls']} | {avg_ns:.0f} | {st['MinNs']} | "
                     f"{st['MaxNs']} |\n\n")
-            f.write(f"Algorithmic bytes per launch: {P_ALG} (4N + 8 per pixel). At the average "
+            f.write(f"Algorithmic bytes per launch: {P_ALG} ({spec.get('y_bytes', 4)}N + 8 per pixel). "
+                    f"At the average "
                     f"duration this is {P_ALG / avg_ns:.1f} GB/s "
                     f"({P_ALG / avg_ns / HBM_PEAK_GBS:.3f} of 8 TB/s).\n\n")
             f.write(f"HBM traffic (FETCH_SIZE and WRITE_SIZE passes, each scaled by its reading "
@@ -187,8 +196,8 @@ def timed(step, steps, warmup, stream):
             "p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]}
 
 
-def roofline(leg, mean_ms):
-    bytes_per_px = 4 * N + 4 + 4  # read FP32 y once; write int32 brk + FP32 mag
+def roofline(leg, mean_ms, y_bytes=4):
+    bytes_per_px = y_bytes * N + 4 + 4  # read y once; write int32 brk + FP32 mag
     alg_bytes = bytes_per_px * P
     achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -241,6 +250,22 @@ def main():
     log(f"bench: plain leg, warmup {args.warmup}, timing {args.steps} steps")
     tp = timed(step, args.steps, args.warmup, stream)
     log(f"bench: {tp['ms_per_step']:.4f} ms/step wall, kernel mean {tp['mean']:.4f} ms")
+    ref = {k: v.clone() for k, v in out.items()}
+
+    # Mixed-precision leg: FP16-stored tile, FP64 arithmetic.
+    Yh = Y.to(torch.float16)
+    outh = {k: torch.empty_like(v) for k, v in out.items()}
+
+    def hstep():
+        bfm.fit_monitor(Yh, n=n, order=ORDER, freq=FREQ, h=H_FRAC, lam=LAM,
+                        outputs=("brk", "mag"), out_dtype=torch.float32, out=outh)
+
+    log(f"bench: mixed leg (FP16 storage), warmup {args.warmup}, timing {args.steps} steps")
+    th = timed(hstep, args.steps, args.warmup, stream)
+    log(f"bench: mixed {th['ms_per_step']:.4f} ms/step wall, kernel mean {th['mean']:.4f} ms")
+    agree = float((outh["brk"] == ref["brk"]).float().mean())
+    dmag = float((outh["mag"] - ref["mag"]).abs().max())
+    del Yh
 
     # Masked leg: the same tile with NaN at 25% of (time, pixel) positions.
     from paper_1807_01751_amd.synth import apply_missing, make_missing, split_rate
@@ -256,6 +281,24 @@ def main():
     tm = timed(mstep, args.steps, args.warmup, stream)
     log(f"bench: masked {tm['ms_per_step']:.4f} ms/step wall, kernel mean {tm['mean']:.4f} ms")
     del Ym
+
+    # Context (not the metric): the tile's host-to-device transfer from pinned
+    # memory, the phase that dominates the paper's GPU timings.
+    host = torch.empty((N, P), dtype=torch.float32, pin_memory=True)
+    host.copy_(Y)
+    dst = torch.empty_like(Y)
+    h2d = []
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        dst.copy_(host, non_blocking=True)
+        b.record(stream)
+        torch.cuda.synchronize()
+        h2d.append(a.elapsed_time(b))
+    assert torch.equal(dst[:: N // 4], Y[:: N // 4])
+    h2d_ms = sorted(h2d)[1]
+    del host, dst
+    log(f"bench: host-to-device {h2d_ms:.3f} ms for {4 * N * P / 1e9:.3f} GB")
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -284,7 +327,18 @@ def main():
                                              f"{100 * MISSING:.0f}% NaN (half iid, half cloud runs "
                                              "of 3-15 rows), per-pixel Gram and Cholesky",
                                  "missing_fraction": round(miss, 4)},
-                      "roofline": roofline("masked", tm["mean"])}}
+                      "roofline": roofline("masked", tm["mean"])},
+           "mixed": {"value": round(P / (th["ms_per_step"] * 1e-3) / 1e6, 2), "unit": "Mpixel/s",
+                     "ms_per_step": round(th["ms_per_step"], 5), "p50_ms": round(th["p50"], 5),
+                     "p99_ms": round(th["p99"], 5), "dtype": "f64", "storage": "f16",
+                     "config": {"workload": "plain BFAST Monitor, the same tile stored as FP16 "
+                                            "(11 significant bits), FP64 arithmetic"},
+                     "vs_f32_leg": {"brk_agreement": round(agree, 6), "max_abs_dmag": round(dmag, 5)},
+                     "roofline": roofline("mixed", th["mean"], y_bytes=2)},
+           "h2d": {"bytes": 4 * N * P, "ms": round(h2d_ms, 3),
+                   "gb_per_s": round(4 * N * P / (h2d_ms * 1e-3) / 1e9, 1),
+                   "pcie_inclusive_mpixel_s": round(P / ((h2d_ms + tp["mean"]) * 1e-3) / 1e6, 1),
+                   "note": "pinned host tile to device, median of 3; context only"}}
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
         res["cpu_baseline"] = cpu_baseline(Y, args.cpu_seconds)

@@ -182,9 +182,9 @@ int bfm_fit_monitor(bfm_ctx *ctx, const bfm_params *prm, const float *Y, int64_t
  * the rounding of the data itself (BF16 keeps 8 significant bits, FP16 11).
  * ld and ldv count elements.  16-bit series are served by the period-blocked
  * kernels: f in {12, 23, 24} and order <= 4, and additionally on the plain path
- * a window H >= f and a full-rank history design, on the missing-value paths
- * n_hist <= 8192 and ld * 4 * f < 2^31; other parameter sets return
- * BFM_E_UNSUPPORTED.
+ * a window H >= f, a full-rank history design and ld * 2 * f < 2^31, on the
+ * missing-value paths n_hist <= 8192 and ld * 4 * f < 2^31; other parameter
+ * sets return BFM_E_UNSUPPORTED.
  * Errors: those of bfm_fit_monitor, BFM_E_INVAL for an unknown y_dtype, and
  * BFM_E_UNSUPPORTED as above.
  */

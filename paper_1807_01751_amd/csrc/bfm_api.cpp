@@ -319,7 +319,9 @@ int bfm_fit_monitor_typed(bfm_ctx* ctx, const bfm_params* prm, const void* Y, in
     if (lds > ctx->max_lds)
         return fail(BFM_E_UNSUPPORTED, "window H=%d needs %zu B of LDS per workgroup (max %zu)",
                     ops.H, lds, ctx->max_lds);
-    if (it->second.per.F > 0) {
+    // The period-blocked kernel addresses the F rows of a block with 32-bit offsets.
+    const int64_t esize = y_dtype == BFM_Y_F32 ? 4 : 2;
+    if (it->second.per.F > 0 && ld * esize * it->second.per.F < ((int64_t)1 << 31)) {
         bfm::PeriodicArgs a{};
         a.Y = Y;
         a.y_dtype = y_dtype;
@@ -346,8 +348,8 @@ int bfm_fit_monitor_typed(bfm_ctx* ctx, const bfm_params* prm, const void* Y, in
         return BFM_SUCCESS;
     }
     if (narrow)
-        return fail(BFM_E_UNSUPPORTED, "a 16-bit series needs f in {12, 23, 24}, order <= %d and a "
-                    "window H >= f on this path", bfm::kPeriodicMaxOrder);
+        return fail(BFM_E_UNSUPPORTED, "a 16-bit series needs f in {12, 23, 24}, order <= %d, a "
+                    "window H >= f and ld * 2 * f < 2^31 on this path", bfm::kPeriodicMaxOrder);
     const double* d = it->second.dev;
     const size_t nq = ops.q.size(), nw = ops.w.size(), nb = ops.bnd.size();
     bfm::PlainArgs a{};

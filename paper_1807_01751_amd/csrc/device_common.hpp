@@ -86,6 +86,48 @@ __device__ __forceinline__ void put_out(void* base, int64_t idx, double v, int f
         put<float>(base, idx, v);
 }
 
+// One observation of element type T by raw buffer load at a lane offset and a
+// scalar (row) offset, decoded to float32.
+__device__ __forceinline__ float load_at(const float*, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, kLoadNT));
+}
+template <typename T>
+__device__ __forceinline__ float load_at(const T*, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    static_assert(sizeof(T) == 2, "16-bit storage types only");
+    const uint32_t b = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, kLoadNT);
+    return decode(T{}, b);
+}
+
+// Cursor over rows of one pixel column for block-wise streaming: one buffer
+// resource based at the current row, row u ahead of it at the scalar byte
+// offset u * ld * sizeof(T) (the caller keeps the rows of a block below 2^31
+// bytes of offset).  Hands out float32 values.
+template <typename T>
+struct BlockCursorT {
+    using value_type = float;
+    const T* row;
+    int64_t ld;
+    uint32_t ldb;         // ld * sizeof(T)
+    uint32_t lane_bytes;  // lane * sizeof(T)
+    __amdgpu_buffer_rsrc_t rsrc;
+    __device__ BlockCursorT(const T* row_, int64_t ld_, uint32_t lane)
+        : row(row_), ld(ld_), ldb((uint32_t)ld_ * (uint32_t)sizeof(T)),
+          lane_bytes(lane * (uint32_t)sizeof(T)), rsrc(row_rsrc(row_))
+    {
+    }
+    __device__ __forceinline__ value_type load(int u) const
+    {
+        return load_at(static_cast<const T*>(nullptr), rsrc, lane_bytes, (uint32_t)u * ldb);
+    }
+    __device__ __forceinline__ void advance(int k)
+    {
+        row += (int64_t)k * ld;
+        rsrc = row_rsrc(row);
+    }
+};
+
 // Cursor over one pixel column of the time-major series (stored as T: float or
 // bf16_t); it hands out float32 values.
 template <typename T>
@@ -200,14 +242,15 @@ __device__ __forceinline__ void stream_aligned(Cursor cur, int t0, int t1, Body&
 {
     using V = typename Cursor::value_type;
     if (t0 >= t1) return;
+    // A partial block reads its rows [lo, hi); the other positions re-read the
+    // nearest of them (never handed over), so both forms are straight-line code.
     auto load_block = [&](V* buf, int lo, int hi) {
         if (lo == 0 && hi == F) {
 #pragma unroll
             for (int u = 0; u < F; ++u) buf[u] = cur.load(u);
         } else {
 #pragma unroll
-            for (int u = 0; u < F; ++u)
-                if (u >= lo && u < hi) buf[u] = cur.load(u - lo);
+            for (int u = 0; u < F; ++u) buf[u] = cur.load(u < lo ? 0 : (u < hi ? u - lo : hi - 1 - lo));
         }
         cur.advance(hi - lo);
     };

@@ -156,20 +156,6 @@ __device__ __forceinline__ void stream_blocks(At at, int t0, int t1, Body&& body
     }
 }
 
-// One observation of element type T (float32, BF16 or FP16) by raw buffer load,
-// decoded to float32.
-__device__ __forceinline__ float load_at(const float*, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
-{
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, kLoadNT));
-}
-template <typename T>
-__device__ __forceinline__ float load_at(const T*, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
-{
-    static_assert(sizeof(T) == 2, "16-bit storage types only");
-    const uint32_t b = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, kLoadNT);
-    return decode(T{}, b);
-}
-
 // Rows tb, tb + 1, ... of the series from one buffer resource based at row tb:
 // row u of the block is at byte offset u * ld * sizeof(T) (a scalar offset), the
 // lane's pixel at lane * sizeof(T).  The host keeps F rows of offsets below 2^31.

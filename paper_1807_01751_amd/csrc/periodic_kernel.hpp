@@ -85,10 +85,10 @@ void periodic_kernel(PeriodicArgs a)
     // Rows from a block boundary at or before n - H also go to the ring, so that
     // it holds the last H history rows when the history ends.
     const int B = ((n - H) / F) * F;
-    stream_aligned<F>(ObsCursorT<T>{Y, ld, lane_bytes}, 0, B, hist, hist_pre);
+    stream_aligned<F>(BlockCursorT<T>(Y, ld, lane), 0, B, hist, hist_pre);
     int slot = B % H;  // ring slot of the next row: t mod H
     stream_aligned<F>(
-        ObsCursorT<T>{Y + (int64_t)B * ld, ld, lane_bytes}, B, n,
+        BlockCursorT<T>(Y + (int64_t)B * ld, ld, lane), B, n,
         [&](int u, int t, float v) {
             hist(u, t, v);
             myring[slot * kPlainBlock] = v;
@@ -217,9 +217,9 @@ void periodic_kernel(PeriodicArgs a)
     const int t_flat = n + a.m_flat;
     const int tA = t_flat >= N ? N : (t_flat / F) * F > n ? (t_flat / F) * F : n;
     const double thr_flat = a.lambda * scale;
-    stream_aligned<F>(ObsCursorT<T>{Y + (int64_t)n * ld, ld, lane_bytes}, n, tA,
+    stream_aligned<F>(BlockCursorT<T>(Y + (int64_t)n * ld, ld, lane), n, tA,
                       [&](int u, int t, float v) { row(u, t, v, thr_flat); }, pre_w);
-    stream_aligned<F>(ObsCursorT<T>{Y + (int64_t)tA * ld, ld, lane_bytes}, tA, N,
+    stream_aligned<F>(BlockCursorT<T>(Y + (int64_t)tA * ld, ld, lane), tA, N,
                       [&](int u, int t, float v) { row(u, t, v, bnd[t - n] * scale); }, pre_w);
 
     const bool bad = hist_bad || !isfinite(Sp);
