@@ -193,6 +193,111 @@ int bfm_fit_monitor_typed(bfm_ctx *ctx, const bfm_params *prm, const void *Y, in
                           const bfm_outputs *out, void *stream);
 
 /*
+ * Serving.  A server runs requests of different sizes and parameters as they
+ * arrive, several at a time: each admitted request runs on one of `slots` HIP
+ * streams of the server's device (non-blocking, default priority), so the work
+ * of requests that arrive while others are on the GPU overlaps with theirs.  A
+ * request is admitted, in arrival order, when a stream is free and its outputs
+ * fit in the server's device pool (pool_bytes, allocated once at creation: no
+ * allocation happens per request).  The shared operators of each parameter set
+ * are built once and stay on the device (Section 3 builds the shared matrix
+ * once for all pixels).  Results are exactly those of bfm_fit_monitor_typed on
+ * the same request.  Thread-safe: any host thread may submit, wait and release.
+ */
+typedef struct bfm_server bfm_server;
+
+/* output selection of a request (brk is always produced) */
+#define BFM_WANT_MAG 1u
+#define BFM_WANT_SIGMA 2u
+#define BFM_WANT_STATUS 4u
+#define BFM_WANT_BETA 8u
+#define BFM_WANT_RESID 16u
+#define BFM_WANT_MOSUM 32u
+
+/*
+ * A request: the arguments of bfm_fit_monitor_typed without the outputs.  Y
+ * (and valid) are caller-owned device memory that must stay unchanged until the
+ * request completes.  `outputs` selects the arrays the server allocates in its
+ * pool, in element type out_dtype (BFM_OUT_F32 or BFM_OUT_F64).
+ */
+typedef struct {
+    bfm_params prm;
+    const void *Y;
+    int32_t y_dtype;
+    int64_t P;
+    int64_t ld;
+    const uint8_t *valid;
+    int64_t ldv;
+    uint32_t outputs;
+    int32_t out_dtype;
+} bfm_request;
+
+/* Completion record of a request. */
+typedef struct {
+    int32_t rc;         /* BFM_SUCCESS, or the error code of the request's launch */
+    bfm_outputs out;    /* server-owned device arrays (NULL where not selected),
+                           valid until bfm_server_release */
+    double queued_us;   /* host time from submit to admission */
+    double latency_us;  /* host time from submit to observed completion */
+    double device_us;   /* time between events around the launch on its stream */
+} bfm_result;
+
+/* Pool bytes a request's outputs occupy (each array 256-byte aligned).
+ * Errors: BFM_E_INVAL (NULL arguments, unknown output bits or out_dtype). */
+int bfm_request_bytes(const bfm_request *req, size_t *bytes);
+
+/*
+ * Create a server on HIP device `device` with `slots` streams (1..64) and a
+ * device pool of pool_bytes.  Errors: BFM_E_INVAL, BFM_E_NODEVICE,
+ * BFM_E_UNSUPPORTED (not gfx950), BFM_E_NOMEM, BFM_E_HIP.
+ */
+int bfm_server_create(bfm_server **out, int device, int slots, size_t pool_bytes);
+
+/*
+ * Queue a request; returns at once with a ticket (> 0).  Parameters are
+ * validated here: BFM_E_INVAL / BFM_E_LAYOUT as for bfm_fit_monitor_typed, and
+ * BFM_E_NOMEM if the request's outputs exceed the whole pool.  Errors found at
+ * launch (e.g. BFM_E_UNSUPPORTED) are reported in the result.
+ */
+int bfm_server_submit(bfm_server *s, const bfm_request *req, uint64_t *ticket);
+
+/*
+ * Wait up to timeout_ms (< 0: without limit) for a request to complete and fill
+ * *res.  Returns BFM_SUCCESS when it completed (its own outcome is res->rc),
+ * BFM_E_INVAL for an unknown or released ticket, or BFM_E_HIP on timeout
+ * (bfm_last_error says so).
+ */
+int bfm_server_wait(bfm_server *s, uint64_t ticket, int timeout_ms, bfm_result *res);
+
+/* Return a completed request's outputs to the pool.  Errors: BFM_E_INVAL
+ * (unknown ticket, or the request has not completed). */
+int bfm_server_release(bfm_server *s, uint64_t ticket);
+
+/*
+ * Copy a completed request's outputs into caller device arrays (the non-NULL
+ * pointers of dst among those the request selected; dst->out_dtype must match
+ * the request's), on `stream`, wait for the copies and release the request.
+ * Errors: BFM_E_INVAL (unknown or not completed ticket, failed request, dtype
+ * mismatch), BFM_E_HIP.
+ */
+int bfm_server_take(bfm_server *s, uint64_t ticket, const bfm_outputs *dst, void *stream);
+
+/* Counters of a server: requests queued, running and completed-unreleased,
+ * pool bytes in use, and the largest number of requests that ran at once. */
+typedef struct {
+    int64_t queued;
+    int64_t running;
+    int64_t completed;
+    int64_t pool_in_use;
+    int64_t max_running;
+} bfm_server_stats;
+int bfm_server_get_stats(bfm_server *s, bfm_server_stats *st);
+
+/* Wait for every admitted request to finish, then release the server (queued
+ * requests are dropped, outputs freed).  NULL is accepted. */
+int bfm_server_destroy(bfm_server *s);
+
+/*
  * Host-only view of the shared operators the plain path streams against, for
  * inspection and tests (no device needed).  With p = 2 + 2k, M = N - n:
  *   q     host double[N * p]: row t is q_t = R^-T x~_t, where x~_t is the

@@ -32,7 +32,11 @@ _ERRNAMES = {E_INVAL: "BFM_E_INVAL", E_LAYOUT: "BFM_E_LAYOUT", E_NOMEM: "BFM_E_N
 
 # Every symbol include/bfm.h declares.
 EXPORTS = ("bfm_version", "bfm_last_error", "bfm_check_params", "bfm_create", "bfm_destroy",
-           "bfm_fit_monitor", "bfm_fit_monitor_typed", "bfm_host_operators")
+           "bfm_fit_monitor", "bfm_fit_monitor_typed", "bfm_host_operators", "bfm_request_bytes",
+           "bfm_server_create", "bfm_server_submit", "bfm_server_wait", "bfm_server_release",
+           "bfm_server_take",
+           "bfm_server_get_stats", "bfm_server_destroy")
+WANT = {"mag": 1, "sigma": 2, "status": 4, "beta": 8, "resid": 16, "mosum": 32}
 
 
 class BfmError(RuntimeError):
@@ -68,6 +72,35 @@ class Outputs(ctypes.Structure):
     ]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("prm", Params),
+        ("Y", ctypes.c_void_p),
+        ("y_dtype", ctypes.c_int32),
+        ("P", ctypes.c_int64),
+        ("ld", ctypes.c_int64),
+        ("valid", ctypes.c_void_p),
+        ("ldv", ctypes.c_int64),
+        ("outputs", ctypes.c_uint32),
+        ("out_dtype", ctypes.c_int32),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("rc", ctypes.c_int32),
+        ("out", Outputs),
+        ("queued_us", ctypes.c_double),
+        ("latency_us", ctypes.c_double),
+        ("device_us", ctypes.c_double),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("queued", "running", "completed", "pool_in_use",
+                                             "max_running")]
+
+
 _lib = None
 _lock = threading.Lock()
 _ctx = {}
@@ -93,6 +126,15 @@ def load():
     lib.bfm_fit_monitor_typed.argtypes = [vp, P_, vp, ctypes.c_int32, i64, i64, vp, i64,
                                           ctypes.POINTER(Outputs), vp]
     lib.bfm_host_operators.argtypes = [P_, vp, vp, vp, vp]
+    R_ = ctypes.POINTER(Request)
+    lib.bfm_request_bytes.argtypes = [R_, ctypes.POINTER(ctypes.c_size_t)]
+    lib.bfm_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_size_t]
+    lib.bfm_server_submit.argtypes = [vp, R_, ctypes.POINTER(ctypes.c_uint64)]
+    lib.bfm_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(Result)]
+    lib.bfm_server_release.argtypes = [vp, ctypes.c_uint64]
+    lib.bfm_server_take.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Outputs), vp]
+    lib.bfm_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.bfm_server_destroy.argtypes = [vp]
     _lib = lib
     return lib
 
@@ -213,3 +255,103 @@ def fit_monitor(Y: torch.Tensor, *, n: int, order: int = 3, freq: float = 23.0, 
                                       vptr, ldv, ctypes.byref(o), s.cuda_stream)
     _raise(rc)
     return res
+
+
+class Server:
+    """bfm_server_*: requests of different shapes and parameters, run as they
+    arrive on ``slots`` streams of one device, admitted by free stream and by room
+    for their outputs in a device pool of ``pool_bytes`` (allocated once).
+
+    ``submit`` takes the same arguments as ``fit_monitor`` (without ``out``) and
+    returns a ticket at once; ``result`` waits for it and returns its outputs as
+    new tensors (bfm_server_take copies them out of the pool and releases it)
+    with its timings.
+    The caller keeps ``Y`` (and ``valid``) alive and unchanged until then.
+    """
+
+    def __init__(self, device: int = 0, slots: int = 4, pool_bytes: int = 1 << 30):
+        h = ctypes.c_void_p()
+        _raise(load().bfm_server_create(ctypes.byref(h), int(device), int(slots), int(pool_bytes)))
+        self.handle = h.value
+        self.device = torch.device("cuda", device)
+        self._pending = {}
+
+    def close(self):
+        if self.handle:
+            load().bfm_server_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def request(self, Y, *, n, order=3, freq=23.0, h=0.25, h_window=0, lam=2.5,
+                mask_mode=MASK_NONE, valid=None, outputs=("brk", "mag"),
+                out_dtype=torch.float64):
+        """The bfm_request for these arguments (no device work)."""
+        if Y.dtype not in _Y_DTYPES or Y.device.type != "cuda":
+            raise ValueError("Y must be a float32, bfloat16 or float16 tensor on a HIP device")
+        Y, N, P, ld = _series_layout(Y)
+        prm = make_params(N, n, order, freq, h, h_window, lam, mask_mode)
+        want = 0
+        for name in outputs:
+            if name != "brk":
+                want |= WANT[name]
+        vptr, ldv = None, 0
+        if mask_mode == MASK_EXPLICIT:
+            if valid is None:
+                raise ValueError("valid is required with MASK_EXPLICIT")
+            valid, _, _, ldv = _series_layout(valid)
+            vptr = valid.data_ptr()
+        return Request(prm, Y.data_ptr(), _Y_DTYPES[Y.dtype], P, ld, vptr, ldv, want,
+                       OUT_F64 if out_dtype == torch.float64 else OUT_F32)
+
+    def submit(self, Y, **kw) -> int:
+        req = self.request(Y, **kw)
+        t = ctypes.c_uint64()
+        _raise(load().bfm_server_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
+        self._pending[t.value] = (req, kw.get("outputs", ("brk", "mag")),
+                                  kw.get("out_dtype", torch.float64))
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> Result:
+        res = Result()
+        _raise(load().bfm_server_wait(self.handle, int(ticket), int(timeout_ms), ctypes.byref(res)))
+        return res
+
+    def result(self, ticket: int, timeout_ms: int = -1) -> dict:
+        """Wait for a request, copy its outputs into new tensors, release it.
+        Returns the outputs plus ``rc`` and the timings in microseconds."""
+        req, outputs, out_dtype = self._pending.pop(ticket)
+        res = self.wait(ticket, timeout_ms)
+        P, N, n, p = req.P, req.prm.n_obs, req.prm.n_hist, 2 + 2 * req.prm.order
+        shapes = {"brk": ((P,), torch.int32), "mag": ((P,), out_dtype), "sigma": ((P,), out_dtype),
+                  "status": ((P,), torch.uint8), "beta": ((p, P), out_dtype),
+                  "resid": ((N, P), out_dtype), "mosum": ((N - n, P), out_dtype)}
+        out = {"rc": res.rc, "queued_us": res.queued_us, "latency_us": res.latency_us,
+               "device_us": res.device_us}
+        if res.rc != SUCCESS:
+            _raise(load().bfm_server_release(self.handle, int(ticket)))
+            return out
+        for name in set(outputs) | {"brk"}:
+            shp, dt = shapes[name]
+            out[name] = torch.empty(shp, dtype=dt, device=self.device)
+        dst = Outputs(*(out[k].data_ptr() if k in out else None
+                        for k in ("brk", "mag", "sigma", "status", "beta", "resid", "mosum")),
+                      req.out_dtype)
+        s = torch.cuda.current_stream(self.device)
+        _raise(load().bfm_server_take(self.handle, int(ticket), ctypes.byref(dst), s.cuda_stream))
+        return out
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _raise(load().bfm_server_get_stats(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}

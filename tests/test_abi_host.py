@@ -128,3 +128,46 @@ def test_host_operators_rank_deficient(bfm):
     with pytest.raises(bfm.BfmError) as e:
         bfm.host_operators(prm)
     assert e.value.code == bfm.E_UNSUPPORTED
+
+
+def _struct_fields(name):
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\} " + name + ";", src, re.S).group(1)
+    return re.findall(r"(\w+);", body)
+
+
+def test_serving_structs_match_header(bfm):
+    assert _struct_fields("bfm_request") == [f[0] for f in bfm.Request._fields_]
+    assert _struct_fields("bfm_result") == [f[0] for f in bfm.Result._fields_]
+    assert _struct_fields("bfm_server_stats") == [f[0] for f in bfm.ServerStats._fields_]
+
+
+def test_request_bytes_layout(bfm):
+    """Pool bytes of a request: each selected output rounded up to 256 bytes."""
+    lib = bfm.load()
+    up = lambda b: (b + 255) // 256 * 256
+    for P, N, n, k, want, f64 in [(1000, 400, 200, 3, 0, 0), (777, 228, 114, 2, 1 | 2 | 4, 1),
+                                  (4096, 300, 150, 4, 63, 0), (0, 100, 50, 1, 63, 1)]:
+        req = bfm.Request(bfm.make_params(N, n, k), None, bfm.Y_F32, P, P, None, 0, want, f64)
+        nb = ctypes.c_size_t()
+        assert lib.bfm_request_bytes(ctypes.byref(req), ctypes.byref(nb)) == 0
+        e = 8 if f64 else 4
+        p = 2 + 2 * k
+        sizes = [4 * P] + [s for bit, s in [(1, e * P), (2, e * P), (4, P), (8, e * p * P),
+                                             (16, e * N * P), (32, e * (N - n) * P)] if want & bit]
+        assert nb.value == sum(up(s) for s in sizes)
+    bad = bfm.Request(bfm.make_params(100, 50, 1), None, 0, 10, 10, None, 0, 64, 0)
+    assert lib.bfm_request_bytes(ctypes.byref(bad), ctypes.byref(nb)) == bfm.E_INVAL
+    bad.outputs, bad.out_dtype = 1, 5
+    assert lib.bfm_request_bytes(ctypes.byref(bad), ctypes.byref(nb)) == bfm.E_INVAL
+
+
+def test_server_create_without_device_reports_nodevice(bfm):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    h = ctypes.c_void_p()
+    lib = bfm.load()
+    assert lib.bfm_server_create(ctypes.byref(h), 0, 4, 1 << 20) == bfm.E_NODEVICE and not h.value
+    assert lib.bfm_server_create(ctypes.byref(h), 0, 0, 1 << 20) == bfm.E_INVAL
+    assert lib.bfm_server_destroy(None) == 0

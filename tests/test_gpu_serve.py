@@ -1,0 +1,127 @@
+"""GPU tests of the serving runtime (bfm_server_*): a mix of requests of
+different sizes, lengths, orders, missing rates and storage types, submitted
+together and run concurrently, gives every request exactly the results it gets
+alone; admission respects the pool; timings are consistent."""
+import sys
+import threading
+
+import numpy as np
+import pytest
+import torch
+
+from parity import to_numpy
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bfm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1807_01751_amd import bfm as b
+    b.load()
+    return b
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def payload(P, N, order, miss, seed, dtype=torch.float32):
+    from paper_1807_01751_amd.synth import apply_missing, make_missing, make_series, split_rate
+    n = N // 2
+    Y, _ = make_series(P, N, n, max(order, 1), seed=seed, step_frac=0.15, device="cuda")
+    if miss > 0:
+        r = split_rate(miss)
+        Y = apply_missing(Y, make_missing(N, P, iid=r, runs=r, seed=seed + 1, device="cuda"))
+    return Y.to(dtype), n
+
+
+def mix(count=24, seed=0):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        P = int(np.exp(rng.uniform(np.log(1000), np.log(120000))))
+        N = int(rng.integers(200, 601))
+        order = int(rng.choice([2, 3, 4]))
+        miss = float(rng.choice([0.0, rng.uniform(0.05, 0.4)]))
+        dtype = [torch.float32, torch.float32, torch.float16][i % 3]
+        Y, n = payload(P, N, order, miss, 1000 + i, dtype)
+        kw = dict(n=n, order=order, mask_mode=1 if miss > 0 else 0,
+                  outputs=("brk", "mag", "sigma", "status"), out_dtype=torch.float64)
+        reqs.append((Y, kw))
+    return reqs
+
+
+def test_mix_equals_alone(bfm):
+    reqs = mix()
+    say(f"case serve mix of {len(reqs)} requests, sizes {[Y.shape[1] for Y, _ in reqs]}")
+    alone = []
+    for Y, kw in reqs:
+        alone.append(to_numpy(bfm.fit_monitor(Y, **kw)))
+    torch.cuda.synchronize()
+    # a pool that holds only some of the requests at once
+    sizes = []
+    with bfm.Server(slots=4, pool_bytes=1 << 20) as probe:
+        for Y, kw in reqs:
+            import ctypes
+            nb = ctypes.c_size_t()
+            r = probe.request(Y, **kw)
+            assert bfm.load().bfm_request_bytes(ctypes.byref(r), ctypes.byref(nb)) == 0
+            sizes.append(nb.value)
+    pool = max(sizes) + sum(sorted(sizes)[:3])
+    with bfm.Server(slots=4, pool_bytes=pool) as srv:
+        tickets = [srv.submit(Y, **kw) for Y, kw in reqs]
+        res = [srv.result(t) for t in tickets]
+        st = srv.stats()
+    say("serve stats", st, "pool", pool)
+    assert st["max_running"] > 1, "requests did not overlap"
+    assert st["pool_in_use"] == 0 and st["running"] == 0 and st["queued"] == 0
+    for i, (r, a) in enumerate(zip(res, alone)):
+        assert r["rc"] == 0, (i, r["rc"])
+        assert 0 <= r["queued_us"] <= r["latency_us"] and r["device_us"] > 0
+        g = to_numpy({k: r[k] for k in a})
+        for k in a:
+            np.testing.assert_array_equal(g[k], a[k], err_msg=f"request {i} {k}")
+
+
+def test_threads_submit_concurrently(bfm):
+    """Four host threads submit and collect their own requests on one server."""
+    reqs = mix(count=12, seed=7)
+    alone = [to_numpy(bfm.fit_monitor(Y, **kw)) for Y, kw in reqs]
+    torch.cuda.synchronize()
+    out = [None] * len(reqs)
+    errors = []
+    with bfm.Server(slots=3, pool_bytes=256 << 20) as srv:
+        def work(idx):
+            try:
+                ts = [(i, srv.submit(reqs[i][0], **reqs[i][1])) for i in idx]
+                for i, t in ts:
+                    out[i] = srv.result(t)
+            except Exception as e:  # reported below
+                errors.append(e)
+        th = [threading.Thread(target=work, args=(list(range(j, len(reqs), 4)),)) for j in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+    assert not errors, errors
+    for i, a in enumerate(alone):
+        for k in a:
+            np.testing.assert_array_equal(out[i][k].cpu().numpy(), a[k], err_msg=f"{i} {k}")
+
+
+def test_admission_errors(bfm):
+    Y, n = payload(5000, 300, 3, 0.0, 5)
+    with bfm.Server(slots=2, pool_bytes=4096) as srv:
+        with pytest.raises(bfm.BfmError) as e:
+            srv.submit(Y, n=n, outputs=("brk", "mag", "mosum"))
+        assert e.value.code == bfm.E_NOMEM
+        with pytest.raises(bfm.BfmError) as e:
+            srv.submit(Y, n=300)  # n must be below N
+        assert e.value.code == bfm.E_INVAL
+    with bfm.Server(slots=2, pool_bytes=64 << 20) as srv:
+        t = srv.submit(Y.to(torch.bfloat16), n=n, freq=22.5)  # fails at launch
+        r = srv.result(t)
+        assert r["rc"] == bfm.E_UNSUPPORTED
+        assert srv.stats()["pool_in_use"] == 0
