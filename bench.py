@@ -13,7 +13,9 @@ After the headline leg, the same tile with 25% of its observations missing
 masked path (per-pixel Gram and Cholesky); it is reported under "masked".  The
 mixed-precision leg ("mixed") stores the tile in FP16 (half the bytes) with the
 same FP64 arithmetic, and reports how its break indices and magnitudes compare
-with the float32 leg.
+with the float32 leg.  A serving leg ("serving") runs a stream of requests of
+mixed sizes and parameters through the serving runtime under Poisson arrivals
+and reports latency percentiles beside throughput.
 
 Prints one JSON line.  Run with --gpus 1 (the default); more GPUs are not
 supported by this benchmark.
@@ -196,6 +198,83 @@ def timed(step, steps, warmup, stream):
             "p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]}
 
 
+def serving_leg(bfm, dev, requests=400, payloads=24, slots=4, load=0.8, seed=5):
+    """Continuous batching under Poisson arrivals (the serving workload scaled to
+    one bench run): requests of log-uniform pixel count in [256^2, 1024^2],
+    N ~ U{200..600}, n = N/2, k in {2, 3, 4}, missing rate 0 or U(0.05, 0.4),
+    15% planted steps, each on one of ``payloads`` device-resident tiles
+    generated before timing.  First the capacity is measured with every request
+    queued at once; then requests arrive as a Poisson process at ``load`` times
+    that capacity.  Latency = submit to completion (server clock)."""
+    import ctypes
+    import math
+    import random
+
+    import numpy as np
+    import torch
+
+    from paper_1807_01751_amd.synth import apply_missing, make_missing, make_series, split_rate
+    rng = np.random.default_rng(seed)
+    tiles = []
+    for i in range(payloads):
+        P = int(math.exp(rng.uniform(math.log(256 ** 2), math.log(1024 ** 2))))
+        N = int(rng.integers(200, 601))
+        order = int(rng.choice([2, 3, 4]))
+        miss = 0.0 if rng.random() < 0.3 else float(rng.uniform(0.05, 0.4))
+        Yt, _ = make_series(P, N, N // 2, order, seed=seed * 100 + i, step_frac=0.15, device=dev)
+        if miss > 0:
+            r = split_rate(miss)
+            Yt = apply_missing(Yt, make_missing(N, P, iid=r, runs=r, seed=seed * 100 + i, device=dev))
+        tiles.append((Yt, order, 1 if miss > 0 else 0))
+    torch.cuda.synchronize()
+    lib = bfm.load()
+    with bfm.Server(device=dev.index or 0, slots=slots, pool_bytes=1 << 30) as srv:
+        reqs = []
+        for j in range(requests):
+            Yt, order, mode = tiles[j % payloads]
+            reqs.append(srv.request(Yt, n=Yt.shape[0] // 2, order=order, mask_mode=mode,
+                                    outputs=("brk", "mag"), out_dtype=torch.float32))
+        pixels = sum(r.P for r in reqs)
+
+        def run(gaps):
+            tickets = []
+            t = ctypes.c_uint64()
+            t0 = time.perf_counter()
+            due = t0
+            for r, g in zip(reqs, gaps):
+                due += g
+                while time.perf_counter() < due:
+                    pass
+                rc = lib.bfm_server_submit(srv.handle, ctypes.byref(r), ctypes.byref(t))
+                assert rc == 0, rc
+                tickets.append(t.value)
+            res, lat = bfm.Result(), []
+            for tk in tickets:
+                assert lib.bfm_server_wait(srv.handle, tk, -1, ctypes.byref(res)) == 0 and res.rc == 0
+                lat.append(res.latency_us)
+                lib.bfm_server_release(srv.handle, tk)
+            return time.perf_counter() - t0, sorted(lat)
+
+        run([0.0] * len(reqs))  # warm: operators of every parameter set built once
+        wall, _ = run([0.0] * len(reqs))
+        capacity = len(reqs) / wall
+        rnd = random.Random(seed)
+        gaps = [rnd.expovariate(load * capacity) for _ in reqs]
+        wall2, lat = run(gaps)
+        st = srv.stats()
+    del tiles
+    q = lambda f: lat[min(len(lat) - 1, int(round(f * (len(lat) - 1))))] / 1e3
+    return {"requests": len(reqs), "slots": slots, "offered_load": load,
+            "capacity_requests_per_s": round(capacity, 1),
+            "saturated_mpixel_s": round(pixels / wall / 1e6, 1),
+            "mpixel_s": round(pixels / wall2 / 1e6, 1), "p50_ms": round(q(0.5), 4),
+            "p99_ms": round(q(0.99), 4), "max_running": st["max_running"],
+            "config": {"workload": "Poisson arrivals of tiles of 256^2-1024^2 pixels, N 200-600, "
+                                   "n = N/2, k 2-4, missing 0 or 5-40% (30% complete), "
+                                   f"{payloads} device-resident payloads reused",
+                       "pixels_total": pixels}}
+
+
 def roofline(leg, mean_ms, y_bytes=4):
     bytes_per_px = y_bytes * N + 4 + 4  # read y once; write int32 brk + FP32 mag
     alg_bytes = bytes_per_px * P
@@ -285,6 +364,11 @@ def main():
     log(f"bench: masked {tm['ms_per_step']:.4f} ms/step wall, kernel mean {tm['mean']:.4f} ms")
     del Ym
 
+    log("bench: serving leg (Poisson arrivals, continuous batching)")
+    serving = serving_leg(bfm, dev)
+    log(f"bench: serving {serving['mpixel_s']} Mpixel/s, p50 {serving['p50_ms']} ms, "
+        f"p99 {serving['p99_ms']} ms, max running {serving['max_running']}")
+
     # Context (not the metric): the tile's host-to-device transfer from pinned
     # memory, the phase that dominates the paper's GPU timings.
     host = torch.empty((N, P), dtype=torch.float32, pin_memory=True)
@@ -338,6 +422,7 @@ def main():
                                             "(11 significant bits), FP64 arithmetic"},
                      "vs_f32_leg": {"brk_agreement": round(agree, 6), "max_abs_d_abs_mag": round(dmag, 5)},
                      "roofline": roofline("mixed", th["mean"], y_bytes=2)},
+           "serving": serving,
            "h2d": {"bytes": 4 * N * P, "ms": round(h2d_ms, 3),
                    "gb_per_s": round(4 * N * P / (h2d_ms * 1e-3) / 1e9, 1),
                    "pcie_inclusive_mpixel_s": round(P / ((h2d_ms + tp["mean"]) * 1e-3) / 1e6, 1),
