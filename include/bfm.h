@@ -193,6 +193,27 @@ int bfm_fit_monitor_typed(bfm_ctx *ctx, const bfm_params *prm, const void *Y, in
                           const bfm_outputs *out, void *stream);
 
 /*
+ * Tile-shape tuning of the plain path.  For f in {12, 23, 24}, a float32
+ * series and no per-row exports (resid, mosum), the plain path may give each
+ * group of 64 pixels 1, 2, 4 or 8 waves that stream consecutive
+ * shares of its rows (the history sums add up over the shares; each share of
+ * the monitoring period rebuilds its MOSUM window from the H rows before it):
+ * a long series over few pixels then finishes sooner.  By default each group
+ * of 64 pixels has one wave (the fastest for the usual tile shapes on MI355X,
+ * measured); bfm_autotune times every
+ * split that fits (on Y, with scratch outputs, synchronising `stream`) and
+ * keeps the fastest for this tile shape (the parameters, y_dtype and the
+ * power-of-two bucket of P/64) in the context; bfm_tune_set pins a split for a
+ * shape.  Results differ between splits only by the rounding of the history
+ * sums.  times_us (nullable, 4 entries) receives the median time of splits 1,
+ * 2, 4, 8 (0 where not run).  Both return BFM_E_UNSUPPORTED where the
+ * parameters do not take the period-blocked plain kernel.
+ */
+int bfm_autotune(bfm_ctx *ctx, const bfm_params *prm, const void *Y, int32_t y_dtype, int64_t P,
+                 int64_t ld, void *stream, int32_t *split, double *times_us);
+int bfm_tune_set(bfm_ctx *ctx, const bfm_params *prm, int32_t y_dtype, int64_t P, int32_t split);
+
+/*
  * Serving.  A server runs requests of different sizes and parameters as they
  * arrive, several at a time: each admitted request runs on one of `slots` HIP
  * streams of the server's device (non-blocking, default priority), so the work

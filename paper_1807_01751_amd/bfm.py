@@ -34,7 +34,7 @@ _ERRNAMES = {E_INVAL: "BFM_E_INVAL", E_LAYOUT: "BFM_E_LAYOUT", E_NOMEM: "BFM_E_N
 EXPORTS = ("bfm_version", "bfm_last_error", "bfm_check_params", "bfm_create", "bfm_destroy",
            "bfm_fit_monitor", "bfm_fit_monitor_typed", "bfm_host_operators", "bfm_request_bytes",
            "bfm_server_create", "bfm_server_submit", "bfm_server_wait", "bfm_server_release",
-           "bfm_server_take",
+           "bfm_server_take", "bfm_autotune", "bfm_tune_set",
            "bfm_server_get_stats", "bfm_server_destroy")
 WANT = {"mag": 1, "sigma": 2, "status": 4, "beta": 8, "resid": 16, "mosum": 32}
 
@@ -126,6 +126,9 @@ def load():
     lib.bfm_fit_monitor_typed.argtypes = [vp, P_, vp, ctypes.c_int32, i64, i64, vp, i64,
                                           ctypes.POINTER(Outputs), vp]
     lib.bfm_host_operators.argtypes = [P_, vp, vp, vp, vp]
+    lib.bfm_autotune.argtypes = [vp, P_, vp, ctypes.c_int32, i64, i64, vp, ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_double)]
+    lib.bfm_tune_set.argtypes = [vp, P_, ctypes.c_int32, i64, ctypes.c_int32]
     R_ = ctypes.POINTER(Request)
     lib.bfm_request_bytes.argtypes = [R_, ctypes.POINTER(ctypes.c_size_t)]
     lib.bfm_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_size_t]
@@ -255,6 +258,30 @@ def fit_monitor(Y: torch.Tensor, *, n: int, order: int = 3, freq: float = 23.0, 
                                       vptr, ldv, ctypes.byref(o), s.cuda_stream)
     _raise(rc)
     return res
+
+
+def autotune(Y: torch.Tensor, *, n: int, order: int = 3, freq: float = 23.0, h: float = 0.25,
+             h_window: int = 0, lam: float = 2.5, stream=None):
+    """bfm_autotune: time the row splits of the plain path on Y and keep the
+    fastest for this tile shape.  Returns (split, {split: median us})."""
+    Y, N, P, ld = _series_layout(Y)
+    dev = Y.device.index if Y.device.index is not None else torch.cuda.current_device()
+    prm = make_params(N, n, order, freq, h, h_window, lam, MASK_NONE)
+    s = stream if stream is not None else torch.cuda.current_stream(Y.device)
+    split = ctypes.c_int32()
+    times = (ctypes.c_double * 4)()
+    _raise(load().bfm_autotune(context(dev), ctypes.byref(prm), Y.data_ptr(), _Y_DTYPES[Y.dtype], P, ld,
+                               s.cuda_stream, ctypes.byref(split), times))
+    return split.value, {k: times[i] for i, k in enumerate((1, 2, 4, 8)) if times[i] > 0}
+
+
+def tune_set(Y: torch.Tensor, split: int, *, n: int, order: int = 3, freq: float = 23.0,
+             h: float = 0.25, h_window: int = 0, lam: float = 2.5):
+    """bfm_tune_set: pin the row split of the plain path for Y's tile shape."""
+    Y, N, P, ld = _series_layout(Y)
+    dev = Y.device.index if Y.device.index is not None else torch.cuda.current_device()
+    prm = make_params(N, n, order, freq, h, h_window, lam, MASK_NONE)
+    _raise(load().bfm_tune_set(context(dev), ctypes.byref(prm), _Y_DTYPES[Y.dtype], P, int(split)))
 
 
 class Server:

@@ -1,6 +1,7 @@
 // C ABI of libbfm: argument validation, contexts, the per-parameter-set cache of
 // shared operators, and dispatch to the gfx950 kernels.  Declarations and the
 // contract of every entry point are in include/bfm.h.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -15,6 +16,7 @@
 struct bfm_ctx {
     int device = 0;
     size_t max_lds = 0;  // dynamic LDS bytes one workgroup may use
+    int cus = 0;         // compute units
     std::mutex mu;
     struct Entry {
         bfm::PlainOps ops;
@@ -24,6 +26,10 @@ struct bfm_ctx {
     };
     using Key = std::tuple<int, int, int, int, double, double, double>;
     std::map<Key, Entry> plain;
+    // Autotuned time split of the period-blocked plain kernel, per tile shape:
+    // (order, F, H, N, n, y_dtype, ceil(log2(waves))) -> waves per 64 pixels.
+    using TuneKey = std::tuple<int, int, int, int, int, int, int>;
+    std::map<TuneKey, int> tune;
     struct MEntry {
         bfm::MaskedOps ops;
         double* dev = nullptr;  // x | g | ph
@@ -95,6 +101,85 @@ struct DeviceGuard {
         if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
     }
 };
+
+int log2_ceil(int64_t v)
+{
+    int k = 0;
+    while (((int64_t)1 << k) < v) ++k;
+    return k;
+}
+
+bfm_ctx::TuneKey tune_key(const bfm_params& p, int y_dtype, int64_t P, int H, int F)
+{
+    return bfm_ctx::TuneKey{p.order, F, H, p.n_obs, p.n_hist, y_dtype, log2_ceil((P + 63) / 64)};
+}
+
+// Waves per 64 pixels that share a pixel's rows in the period-blocked plain
+// kernel: the tuned (or pinned) choice for this tile shape, else a rule taken
+// from timings on MI355X.  A tile of at most one wave per compute unit over a
+// series of 512 rows or more runs 2-2.7x faster with eight waves per 64 pixels
+// (4096 or 16384 pixels x 1000-4600 rows); with more waves than compute units,
+// or over shorter series (4096 x 228), one wave per 64 pixels is as fast or
+// faster.
+int choose_split(bfm_ctx* ctx, const bfm_params& p, int y_dtype, int64_t P, int H, int F)
+{
+    auto it = ctx->tune.find(tune_key(p, y_dtype, P, H, F));
+    if (it != ctx->tune.end()) return it->second;
+    const int64_t waves = (P + 63) / 64;
+    if (waves <= ctx->cus && p.n_obs >= 512 &&
+        bfm::periodic_split_lds(p.order, F, 8, H) <= ctx->max_lds)
+        return 8;
+    return 1;
+}
+
+// The plain-path operators of a parameter set (built and copied to the device
+// on first use).  Call with ctx->mu held.
+int plain_entry(bfm_ctx* ctx, const bfm_params& p, bfm_ctx::Entry** out)
+{
+    bfm_ctx::Key key{p.n_obs, p.n_hist, p.order, p.h_window, p.freq, p.h_frac, p.lambda};
+    auto it = ctx->plain.find(key);
+    if (it == ctx->plain.end()) {
+        bfm_ctx::Entry ent;
+        bfm::build_plain_ops(p, &ent.ops);
+        const size_t nq = ent.ops.q.size(), nw = ent.ops.w.size(), nb = ent.ops.bnd.size(),
+                     nm = ent.ops.bmap.size();
+        std::vector<double> host;
+        host.reserve(nq + nw + nb + nm);
+        host.insert(host.end(), ent.ops.q.begin(), ent.ops.q.end());
+        host.insert(host.end(), ent.ops.w.begin(), ent.ops.w.end());
+        host.insert(host.end(), ent.ops.bnd.begin(), ent.ops.bnd.end());
+        host.insert(host.end(), ent.ops.bmap.begin(), ent.ops.bmap.end());
+        hipError_t e = hipMalloc(&ent.dev, host.size() * sizeof(double));
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(operators)");
+        // A synchronous copy: the operator block is a few tens of KB and this
+        // happens once per parameter set.
+        e = hipMemcpy(ent.dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(ent.dev);
+            return hip_fail(e, "hipMemcpy(operators)");
+        }
+        const int F = bfm::periodic_period(p, ent.ops);
+        if (F > 0) {
+            bfm::build_periodic_ops(p, ent.ops, F, &ent.per);
+            std::vector<double> ph(ent.per.rt);
+            ph.insert(ph.end(), ent.per.ri.begin(), ent.per.ri.end());
+            ph.insert(ph.end(), ent.per.hh.begin(), ent.per.hh.end());
+            ph.insert(ph.end(), ent.per.wh.begin(), ent.per.wh.end());
+            ph.insert(ph.end(), ent.ops.bnd.begin(), ent.ops.bnd.end());
+            e = hipMalloc(&ent.pdev, ph.size() * sizeof(double));
+            if (e == hipSuccess)
+                e = hipMemcpy(ent.pdev, ph.data(), ph.size() * sizeof(double), hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                (void)hipFree(ent.dev);
+                if (ent.pdev) (void)hipFree(ent.pdev);
+                return hip_fail(e, "periodic operators");
+            }
+        }
+        it = ctx->plain.emplace(key, std::move(ent)).first;
+    }
+    *out = &it->second;
+    return BFM_SUCCESS;
+}
 
 // Missing-value modes: per-pixel masked fit (csrc/masked_kernel.hip).
 int fit_masked(bfm_ctx* ctx, const bfm_params& p, const void* Y, int y_dtype, int64_t P, int64_t ld,
@@ -189,6 +274,7 @@ int bfm_create(bfm_ctx** out, int device)
     if (!ctx) return fail(BFM_E_NOMEM, "context allocation failed");
     ctx->device = device;
     ctx->max_lds = prop.sharedMemPerBlock;
+    ctx->cus = prop.multiProcessorCount;
     *out = ctx;
     g_err.clear();
     return BFM_SUCCESS;
@@ -261,47 +347,11 @@ int bfm_fit_monitor_typed(bfm_ctx* ctx, const bfm_params* prm, const void* Y, in
     std::lock_guard<std::mutex> lock(ctx->mu);
     DeviceGuard g(ctx->device);
     if (p.mask_mode != BFM_MASK_NONE) return fit_masked(ctx, p, Y, y_dtype, P, ld, valid, ldv, *out, s);
-    bfm_ctx::Key key{p.n_obs, p.n_hist, p.order, p.h_window, p.freq, p.h_frac, p.lambda};
-    auto it = ctx->plain.find(key);
-    if (it == ctx->plain.end()) {
-        bfm_ctx::Entry ent;
-        bfm::build_plain_ops(p, &ent.ops);
-        const size_t nq = ent.ops.q.size(), nw = ent.ops.w.size(), nb = ent.ops.bnd.size(),
-                     nm = ent.ops.bmap.size();
-        std::vector<double> host;
-        host.reserve(nq + nw + nb + nm);
-        host.insert(host.end(), ent.ops.q.begin(), ent.ops.q.end());
-        host.insert(host.end(), ent.ops.w.begin(), ent.ops.w.end());
-        host.insert(host.end(), ent.ops.bnd.begin(), ent.ops.bnd.end());
-        host.insert(host.end(), ent.ops.bmap.begin(), ent.ops.bmap.end());
-        hipError_t e = hipMalloc(&ent.dev, host.size() * sizeof(double));
-        if (e != hipSuccess) return hip_fail(e, "hipMalloc(operators)");
-        // A synchronous copy: the operator block is a few tens of KB and this
-        // happens once per parameter set.
-        e = hipMemcpy(ent.dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            (void)hipFree(ent.dev);
-            return hip_fail(e, "hipMemcpy(operators)");
-        }
-        const int F = bfm::periodic_period(p, ent.ops);
-        if (F > 0) {
-            bfm::build_periodic_ops(p, ent.ops, F, &ent.per);
-            std::vector<double> ph(ent.per.rt);
-            ph.insert(ph.end(), ent.per.ri.begin(), ent.per.ri.end());
-            ph.insert(ph.end(), ent.per.hh.begin(), ent.per.hh.end());
-            ph.insert(ph.end(), ent.per.wh.begin(), ent.per.wh.end());
-            ph.insert(ph.end(), ent.ops.bnd.begin(), ent.ops.bnd.end());
-            e = hipMalloc(&ent.pdev, ph.size() * sizeof(double));
-            if (e == hipSuccess)
-                e = hipMemcpy(ent.pdev, ph.data(), ph.size() * sizeof(double), hipMemcpyHostToDevice);
-            if (e != hipSuccess) {
-                (void)hipFree(ent.dev);
-                if (ent.pdev) (void)hipFree(ent.pdev);
-                return hip_fail(e, "periodic operators");
-            }
-        }
-        it = ctx->plain.emplace(key, std::move(ent)).first;
-    }
+    bfm_ctx::Entry* ent = nullptr;
+    rc = plain_entry(ctx, p, &ent);
+    if (rc) return rc;
+    auto* it = &*ctx->plain.find(bfm_ctx::Key{p.n_obs, p.n_hist, p.order, p.h_window, p.freq, p.h_frac,
+                                               p.lambda});
     const bfm::PlainOps& ops = it->second.ops;
 
     uint8_t global_st = BFM_ST_OK;
@@ -325,6 +375,9 @@ int bfm_fit_monitor_typed(bfm_ctx* ctx, const bfm_params* prm, const void* Y, in
         bfm::PeriodicArgs a{};
         a.Y = Y;
         a.y_dtype = y_dtype;
+        a.split = y_dtype == BFM_Y_F32 && !out->resid && !out->mosum
+                      ? choose_split(ctx, p, y_dtype, P, ops.H, it->second.per.F)
+                      : 1;
         a.ld = ld;
         a.P = P;
         a.tab = it->second.pdev;
@@ -377,6 +430,106 @@ int bfm_fit_monitor_typed(bfm_ctx* ctx, const bfm_params* prm, const void* Y, in
     a.out_f64 = out->out_dtype == BFM_OUT_F64;
     e = bfm::launch_plain(a, np, s);
     if (e != hipSuccess) return hip_fail(e, "plain kernel launch");
+    return BFM_SUCCESS;
+}
+
+namespace {
+
+// The time split applies: the period-blocked plain kernel serves these parameters.
+int split_shape(bfm_ctx* ctx, const bfm_params* prm, int32_t y_dtype, int64_t P, int64_t ld, int* H,
+                int* F)
+{
+    if (!ctx) return fail(BFM_E_INVAL, "ctx is NULL");
+    int rc = check(prm, P, ld);
+    if (rc) return rc;
+    if (y_dtype != BFM_Y_F32 && y_dtype != BFM_Y_BF16 && y_dtype != BFM_Y_F16)
+        return fail(BFM_E_INVAL, "unknown y_dtype %d", y_dtype);
+    if (prm->mask_mode != BFM_MASK_NONE || y_dtype != BFM_Y_F32)
+        return fail(BFM_E_UNSUPPORTED, "tile tuning applies to the plain path on float32 series");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    DeviceGuard g(ctx->device);
+    bfm_ctx::Entry* ent = nullptr;
+    rc = plain_entry(ctx, *prm, &ent);
+    if (rc) return rc;
+    const int64_t esize = y_dtype == BFM_Y_F32 ? 4 : 2;
+    if (ent->per.F == 0 || !ent->ops.rank_ok || ent->ops.n <= ent->ops.p || ent->ops.H < 1 ||
+        ld * esize * ent->per.F >= ((int64_t)1 << 31))
+        return fail(BFM_E_UNSUPPORTED, "these parameters do not take the period-blocked plain kernel");
+    *H = ent->ops.H;
+    *F = ent->per.F;
+    return BFM_SUCCESS;
+}
+
+}  // namespace
+
+int bfm_tune_set(bfm_ctx* ctx, const bfm_params* prm, int32_t y_dtype, int64_t P, int32_t split)
+{
+    int H = 0, F = 0;
+    int rc = split_shape(ctx, prm, y_dtype, P, P, &H, &F);
+    if (rc) return rc;
+    if (split != 1 && split != 2 && split != 4 && split != 8)
+        return fail(BFM_E_INVAL, "split must be 1, 2, 4 or 8 (got %d)", split);
+    if (bfm::periodic_split_lds(prm->order, F, split, H) > ctx->max_lds)
+        return fail(BFM_E_UNSUPPORTED, "split %d needs more LDS than a workgroup has", split);
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    ctx->tune[tune_key(*prm, y_dtype, P, H, F)] = split;
+    return BFM_SUCCESS;
+}
+
+int bfm_autotune(bfm_ctx* ctx, const bfm_params* prm, const void* Y, int32_t y_dtype, int64_t P,
+                 int64_t ld, void* stream, int32_t* split, double* times_us)
+{
+    int H = 0, F = 0;
+    int rc = split_shape(ctx, prm, y_dtype, P, ld, &H, &F);
+    if (rc) return rc;
+    if (P < 1 || !Y) return fail(BFM_E_INVAL, "autotune needs P >= 1 and Y");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    bfm_outputs out{};
+    out.out_dtype = BFM_OUT_F32;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&out.brk, (size_t)P * 4);
+    if (e == hipSuccess) e = hipMalloc(&out.mag, (size_t)P * 4);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const int cand[4] = {1, 2, 4, 8};
+    double med[4] = {0, 0, 0, 0};
+    int best = 0;
+    const auto key = tune_key(*prm, y_dtype, P, H, F);
+    for (int i = 0; i < 4 && e == hipSuccess && rc == BFM_SUCCESS; ++i) {
+        if (bfm::periodic_split_lds(prm->order, F, cand[i], H) > ctx->max_lds) continue;
+        {
+            std::lock_guard<std::mutex> lock(ctx->mu);
+            ctx->tune[key] = cand[i];
+        }
+        std::vector<double> t;
+        for (int r = 0; r < 7 && rc == BFM_SUCCESS && e == hipSuccess; ++r) {
+            (void)hipEventRecord(e0, st);
+            rc = bfm_fit_monitor_typed(ctx, prm, Y, y_dtype, P, ld, nullptr, 0, &out, st);
+            (void)hipEventRecord(e1, st);
+            e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (r >= 2) t.push_back(1e3 * (double)ms);  // the first two warm up
+        }
+        if (t.empty()) continue;
+        std::sort(t.begin(), t.end());
+        med[i] = t[t.size() / 2];
+        if (med[best] == 0.0 || med[i] < med[best]) best = i;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (out.brk) (void)hipFree(out.brk);
+    if (out.mag) (void)hipFree(out.mag);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    {
+        std::lock_guard<std::mutex> lock(ctx->mu);
+        ctx->tune[key] = cand[best];
+    }
+    if (split) *split = cand[best];
+    if (times_us)
+        for (int i = 0; i < 4; ++i) times_us[i] = med[i];
     return BFM_SUCCESS;
 }
 

@@ -108,6 +108,7 @@ hipError_t launch_plain(const PlainArgs& a, int p, hipStream_t stream);
 struct PeriodicArgs {
     const void* Y;       // element type y_dtype (BFM_Y_*)
     int y_dtype;
+    int split;           // waves per 64 pixels that share the rows: 1, 2, 4 or 8
     int64_t ld;
     int64_t P;
     const double* tab;   // rt | ri | hh | wh | bnd
@@ -123,7 +124,15 @@ struct PeriodicArgs {
     int out_f64;
 };
 hipError_t launch_periodic(const PeriodicArgs& a, int order, int F, hipStream_t stream);
-hipError_t launch_periodic_16(const PeriodicArgs& a, int order, int F, hipStream_t stream);
+// LDS bytes the time-split form needs (0 if the split is not supported).
+size_t periodic_split_lds(int order, int F, int split, int H);
+// The time-split form (float32 series, no per-row exports; a.split in {2, 4, 8}).
+hipError_t launch_periodic_split(const PeriodicArgs& a, int order, int F, hipStream_t stream);
+hipError_t launch_periodic_split2(const PeriodicArgs& a, int order, int F, hipStream_t stream);
+hipError_t launch_periodic_split4(const PeriodicArgs& a, int order, int F, hipStream_t stream);
+hipError_t launch_periodic_split8(const PeriodicArgs& a, int order, int F, hipStream_t stream);
+hipError_t launch_periodic_bf16(const PeriodicArgs& a, int order, int F, hipStream_t stream);
+hipError_t launch_periodic_f16(const PeriodicArgs& a, int order, int F, hipStream_t stream);
 
 // Arguments of the masked kernel (by value; every pointer is device memory).
 struct MaskedArgs {
@@ -151,7 +160,8 @@ struct MaskedArgs {
 
 hipError_t launch_masked(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
 hipError_t launch_masked_periodic(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
-hipError_t launch_masked_periodic_16(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
+hipError_t launch_masked_periodic_bf16(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
+hipError_t launch_masked_periodic_f16(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
 size_t masked_periodic_lds_bytes(int cap);
 size_t masked_lds_bytes(int cap);
 

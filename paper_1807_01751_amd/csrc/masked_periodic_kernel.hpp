@@ -14,8 +14,8 @@
 //
 // The series may be stored as float32, BF16 or FP16 (template parameter T); the
 // arithmetic is the same.  This header holds the kernel template;
-// masked_periodic_kernel.hip (float32) and masked_periodic_kernel_16.hip (BF16,
-// FP16) instantiate it.
+// masked_periodic_kernel.hip (float32), masked_periodic_kernel_bf16.hip and
+// masked_periodic_kernel_f16.hip instantiate it.
 //
 // One lane owns one pixel and streams its series once, time-major, in blocks
 // of F rows aligned to multiples of F, so a row's phase is a compile-time

@@ -1,0 +1,11 @@
+// Period-blocked masked kernel, BF16-stored series (template in masked_periodic_kernel.hpp).
+#include "masked_periodic_kernel.hpp"
+
+namespace bfm {
+
+hipError_t launch_masked_periodic_bf16(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream)
+{
+    return launch_t<dev::bf16_t>(a, order, mask_mode, stream);
+}
+
+}  // namespace bfm

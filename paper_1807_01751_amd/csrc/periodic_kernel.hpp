@@ -20,7 +20,8 @@
 // or FP16 (template parameter T); arithmetic is FP64 either way.
 //
 // This header holds the kernel template; periodic_kernel.hip (float32) and
-// periodic_kernel_16.hip (BF16, FP16) instantiate it.
+// periodic_kernel_bf16.hip, periodic_kernel_f16.hip and periodic_split_*.hip
+// instantiate it.
 #pragma once
 
 #include <climits>
@@ -249,6 +250,296 @@ void periodic_kernel(PeriodicArgs a)
         if (a.mosum && st != BFM_ST_OK)
             for (int m = 0; m < N - n; ++m) put_out(a.mosum, (int64_t)m * a.P + pix, qnan, a.out_f64);
     }
+}
+
+// Time-split form for tiles too small to fill the device: NS waves of one
+// workgroup share 64 pixels and each streams a contiguous share of the history
+// blocks and of the monitoring blocks, so a pixel's rows are worked on NS at a
+// time.  The history sums (phase sums A, yy, Wb, max |y|) add up over the
+// shares: every wave leaves its partial sums in LDS and wave 0 adds them in wave
+// order, fits (the same arithmetic as periodic_kernel) and leaves the per-pixel
+// quantities the monitoring needs in LDS.  Each wave rebuilds the window at the
+// start of its monitoring share from the H rows before it (Eq. 3 needs only
+// them), runs the same per-row recursion, and the first crossing, max and min
+// are combined over the waves at the end.
+//
+// LDS (bytes): max(NS (F + 3) 512, (F + NP + 5) 512 + NS H 256).
+template <int K, int F, int NS, bool EXPORT, typename T>
+__global__ __launch_bounds__(kPlainBlock * NS) void periodic_split_kernel(PeriodicArgs a)
+{
+    constexpr int NP = 2 + 2 * K;
+    constexpr int NH = 2 * K;
+    constexpr int NB = F + NP + 5;  // broadcast doubles per lane: Pw, beta, gamma, Lc, scale, c, sig
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x % kPlainBlock;
+    const int w = threadIdx.x / kPlainBlock;  // wave index: its share of the rows
+    const int64_t pix = (int64_t)blockIdx.x * kPlainBlock + tid;
+    const bool active = pix < a.P;
+    const uint32_t lane = (uint32_t)(active ? pix : a.P - 1);
+    const uint32_t lane_bytes = lane * (uint32_t)sizeof(T);
+    const int n = a.n, N = a.N, H = a.H;
+    const int64_t ld = a.ld;
+    const T* __restrict__ Y = static_cast<const T*>(a.Y);
+    const ctab rt = as_const(a.tab);
+    const ctab ri = rt + NP * NP;
+    const ctab hh = ri + NP * NP;
+    const ctab wh = hh + F * NH;
+    const ctab bnd = wh + F * NH;
+    double* const part = lds + tid;               // [NS][F + 3][64]
+    double* const bc = lds + tid;                  // [NB][64] after the combine
+    float* const myring = reinterpret_cast<float*>(lds + NB * kPlainBlock) + w * H * kPlainBlock + tid;
+
+    // ---- this wave's share of the history blocks ----
+    const double c = (double)load_obs(Y, lane_bytes);
+    const int nbh = (n + F - 1) / F;
+    const int h0 = (nbh * w / NS) * F;
+    const int h1 = min((nbh * (w + 1) / NS) * F, n);
+    double A[F];
+#pragma unroll
+    for (int u = 0; u < F; ++u) A[u] = 0.0;
+    double yy = 0.0, Wb = 0.0, bidx = 0.0;
+    uint32_t ymax_bits = 0;
+    if (h0 < h1)
+        stream_aligned<F>(
+            BlockCursorT<T>(Y + (int64_t)h0 * ld, ld, lane), h0, h1,
+            [&](int u, int, float v) {
+                const double d = (double)v - c;
+                yy = fma(d, d, yy);
+                A[u] += d;
+                Wb = fma(bidx, d, Wb);
+                ymax_bits = max(ymax_bits, __float_as_uint(v) & 0x7fffffffu);
+            },
+            [&](int tb, int, int) { bidx = (double)(tb / F); });
+#pragma unroll
+    for (int u = 0; u < F; ++u) part[((w * (F + 3)) + u) * kPlainBlock] = A[u];
+    part[(w * (F + 3) + F) * kPlainBlock] = yy;
+    part[(w * (F + 3) + F + 1) * kPlainBlock] = Wb;
+    part[(w * (F + 3) + F + 2) * kPlainBlock] = __longlong_as_double((long long)ymax_bits);
+    __syncthreads();
+
+    const double tc = 0.5 * (double)(n + 1);
+    const double qnan = __builtin_nan("");
+    bool hist_bad = false, degenerate = false;
+    double beta[NP];
+    if (w == 0) {
+        // ---- sum of the shares (in wave order) and the fit ----
+        for (int v = 1; v < NS; ++v) {
+#pragma unroll
+            for (int u = 0; u < F; ++u) A[u] += part[(v * (F + 3) + u) * kPlainBlock];
+            yy += part[(v * (F + 3) + F) * kPlainBlock];
+            Wb += part[(v * (F + 3) + F + 1) * kPlainBlock];
+            ymax_bits = max(ymax_bits,
+                            (uint32_t)__double_as_longlong(part[(v * (F + 3) + F + 2) * kPlainBlock]));
+        }
+        double g[NP];
+        double g0 = 0.0;
+#pragma unroll
+        for (int u = 0; u < F; ++u) g0 += A[u];
+        double Tr = (double)F * Wb;
+#pragma unroll
+        for (int u = 0; u < F; ++u) Tr = fma((double)(u + 1), A[u], Tr);
+        g[0] = g0;
+        g[1] = (Tr - 0.5 * (double)(n + 1) * g0) / (double)n;
+#pragma unroll
+        for (int j = 0; j < NH; ++j) {
+            double sj = 0.0;
+#pragma unroll
+            for (int u = 0; u < F; ++u) sj = fma(hh[u * NH + j], A[u], sj);
+            g[2 + j] = sj;
+        }
+        double bq[NP];
+        double rss = yy;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            double sv = 0.0;
+#pragma unroll
+            for (int k = 0; k <= i; ++k) sv = fma(rt[i * NP + k], g[k], sv);
+            bq[i] = sv;
+            rss = fma(-sv, sv, rss);
+        }
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            double sv = 0.0;
+#pragma unroll
+            for (int k = i; k < NP; ++k) sv = fma(ri[i * NP + k], bq[k], sv);
+            beta[i] = sv;
+        }
+        const double sig = sqrt(fmax(rss, 0.0) * a.inv_dof);
+        hist_bad = !isfinite(yy);
+        degenerate = sig <= kSigmaRelTol * (double)__uint_as_float(ymax_bits);
+        const double Hd = (double)H;
+        // per-pixel quantities of the monitoring, for every wave
+#pragma unroll
+        for (int u = 0; u < F; ++u) {
+            double sv = 0.0;
+#pragma unroll
+            for (int j = 0; j < NH; ++j) sv = fma(wh[u * NH + j], beta[2 + j], sv);
+            bc[u * kPlainBlock] = sv;
+        }
+#pragma unroll
+        for (int j = 0; j < NP; ++j) bc[(F + j) * kPlainBlock] = beta[j];
+        bc[(F + NP) * kPlainBlock] = beta[1] * Hd / (double)n;  // gamma
+        bc[(F + NP + 1) * kPlainBlock] = Hd * beta[0] - beta[1] * Hd * (0.5 * (Hd - 1.0) + tc) / (double)n;
+        bc[(F + NP + 2) * kPlainBlock] = sig * a.sqrt_n;  // scale
+        bc[(F + NP + 4) * kPlainBlock] = sig;
+    }
+    __syncthreads();
+    double Pw[F];
+#pragma unroll
+    for (int u = 0; u < F; ++u) Pw[u] = bc[u * kPlainBlock];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) beta[j] = bc[(F + j) * kPlainBlock];
+    const double gamma = bc[(F + NP) * kPlainBlock];
+    const double Lc = bc[(F + NP + 1) * kPlainBlock];
+    const double scale = bc[(F + NP + 2) * kPlainBlock];
+    const double sig = bc[(F + NP + 4) * kPlainBlock];
+    if (w == 0 && active) {
+        if (a.sigma) put_out(a.sigma, pix, hist_bad ? qnan : sig, a.out_f64);
+        if (a.beta)
+            for (int j = 0; j < NP; ++j) {
+                double v = beta[j];
+                if (j == 0) v = beta[0] - (tc / (double)n) * beta[1] + c;
+                if (j == 1) v = beta[1] / (double)n;
+                put_out(a.beta, (int64_t)j * a.P + pix, hist_bad ? qnan : v, a.out_f64);
+            }
+    }
+
+    // ---- this wave's share of the monitoring blocks ----
+    const int mb0 = n / F, nbm = (N - 1) / F - mb0 + 1;
+    const int m0 = max(n, (mb0 + nbm * w / NS) * F);
+    const int m1 = min(N, (mb0 + nbm * (w + 1) / NS) * F);
+    double hi = -INFINITY, lo = INFINITY;
+    int brk = INT_MAX;
+    bool mon_bad = false;
+    if (m0 < m1) {
+        // the window that ends at row m0 - 1: its H rows go to this wave's ring
+        // (row t in slot t mod H) and their sum starts the recursion
+        double Sy = 0.0;
+        int slot = (m0 - H) % H;
+        stream_aligned<F>(
+            BlockCursorT<T>(Y + (int64_t)(m0 - H) * ld, ld, lane), m0 - H, m0,
+            [&](int, int, float v) {
+                myring[slot * kPlainBlock] = v;
+                slot = slot + 1 == H ? 0 : slot + 1;
+                Sy += (double)v - c;
+            },
+            [](int, int, int) {});
+        double Sp = Sy - Lc - gamma * (double)m0;
+        float vo[F];
+        int s0 = slot, wslot = 0;
+        auto pre_w = [&](int, int lo_, int hi_) {
+            s0 = slot;
+#pragma unroll
+            for (int u = 0; u < F; ++u) {
+                if (u >= lo_ && u < hi_) {
+                    int sl = s0 + (u - lo_);
+                    sl -= sl >= H ? H : 0;
+                    vo[u] = myring[sl * kPlainBlock];
+                }
+            }
+            slot = s0 + (hi_ - lo_);
+            slot -= slot >= H ? H : 0;
+            wslot = s0;
+        };
+        auto row = [&](int u, int t, float v, double thr) {
+            myring[wslot * kPlainBlock] = v;
+            wslot = wslot + 1 == H ? 0 : wslot + 1;
+            Sp += ((double)v - (double)vo[u]) - gamma;
+            const double num = Sp - Pw[u];
+            const int m = t - n;
+            brk = fabs(num) > thr ? min(brk, m) : brk;
+            hi = fmax(hi, num);
+            lo = fmin(lo, num);
+            if (EXPORT && a.mosum && active)
+                put_out(a.mosum, (int64_t)m * a.P + lane, num / scale, a.out_f64);
+        };
+        const int t_flat = n + a.m_flat;
+        const double thr_flat = a.lambda * scale;
+        const int mA = min(max(t_flat, m0), m1);
+        if (m0 < mA)
+            stream_aligned<F>(BlockCursorT<T>(Y + (int64_t)m0 * ld, ld, lane), m0, mA,
+                              [&](int u, int t, float v) { row(u, t, v, thr_flat); }, pre_w);
+        if (mA < m1)
+            stream_aligned<F>(BlockCursorT<T>(Y + (int64_t)mA * ld, ld, lane), mA, m1,
+                              [&](int u, int t, float v) { row(u, t, v, bnd[t - n] * scale); }, pre_w);
+        mon_bad = !isfinite(Sp);
+    }
+
+    // ---- combine the shares ----
+    __syncthreads();  // every wave is past its reads of the broadcast area
+    lds[(0 * NS + w) * kPlainBlock + tid] = hi;
+    lds[(1 * NS + w) * kPlainBlock + tid] = lo;
+    lds[(2 * NS + w) * kPlainBlock + tid] = __longlong_as_double((long long)brk | ((long long)mon_bad << 32));
+    __syncthreads();
+    if (w != 0) return;
+    bool bad = hist_bad;
+    for (int v = 0; v < NS; ++v) {
+        hi = fmax(hi, lds[(0 * NS + v) * kPlainBlock + tid]);
+        lo = fmin(lo, lds[(1 * NS + v) * kPlainBlock + tid]);
+        const long long e = __double_as_longlong(lds[(2 * NS + v) * kPlainBlock + tid]);
+        brk = min(brk, (int)(e & 0xffffffffll));
+        bad = bad || ((e >> 32) & 1);
+    }
+    const uint8_t st = bad ? BFM_ST_NONFINITE : degenerate ? BFM_ST_DEGENERATE_SIGMA : BFM_ST_OK;
+    if (!active) return;
+    double mag = qnan;
+    if (st == BFM_ST_OK) mag = (hi >= -lo ? hi : lo) / scale;
+    if (st != BFM_ST_OK || brk == INT_MAX) brk = -1;
+    a.brk[pix] = brk;
+    if (a.mag) put_out(a.mag, pix, mag, a.out_f64);
+    if (a.status) a.status[pix] = st;
+    if (bad && !hist_bad) {
+        if (a.sigma) put_out(a.sigma, pix, qnan, a.out_f64);
+        if (a.beta)
+            for (int j = 0; j < NP; ++j) put_out(a.beta, (int64_t)j * a.P + pix, qnan, a.out_f64);
+    }
+    if (EXPORT) {
+        if (a.resid) {
+            for (int t = 0; t < N; ++t) {
+                double r = qnan;
+                if (st != BFM_ST_NONFINITE) {
+                    const int ph = t % F;
+                    r = (double)to_float(Y[(int64_t)t * ld + pix]) - c - beta[0] -
+                        beta[1] * ((double)(t + 1) - tc) / (double)n;
+                    for (int j = 0; j < NH; ++j) r = fma(-hh[ph * NH + j], beta[2 + j], r);
+                }
+                put_out(a.resid, (int64_t)t * a.P + pix, r, a.out_f64);
+            }
+        }
+        if (a.mosum && st != BFM_ST_OK)
+            for (int m = 0; m < N - n; ++m) put_out(a.mosum, (int64_t)m * a.P + pix, qnan, a.out_f64);
+    }
+}
+
+// LDS bytes of periodic_split_kernel for these sizes.
+__host__ __device__ constexpr size_t split_lds_bytes(int F, int NP, int NS, int H)
+{
+    const size_t partials = (size_t)NS * (F + 3) * kPlainBlock * 8;
+    const size_t monitor = (size_t)(F + NP + 5) * kPlainBlock * 8 + (size_t)NS * H * kPlainBlock * 4;
+    const size_t combine = (size_t)3 * NS * kPlainBlock * 8;
+    size_t m = partials > monitor ? partials : monitor;
+    return m > combine ? m : combine;
+}
+
+// The time-split launches (float32 series, no per-row exports): one
+// translation unit per split factor instantiates them.
+template <int NS>
+hipError_t launch_split_ns(const PeriodicArgs& a, int order, int F, hipStream_t stream)
+{
+    const dim3 grid((unsigned)((a.P + kPlainBlock - 1) / kPlainBlock));
+    const size_t lds = split_lds_bytes(F, 2 + 2 * order, NS, a.H);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(kPlainBlock * NS), lds, stream, a);
+        return hipGetLastError();
+    };
+#define BFM_SPLIT_CASE(K, FF) \
+    if (order == K && F == FF) return go(periodic_split_kernel<K, FF, NS, false, float>);
+#define BFM_SPLIT_F(FF) BFM_SPLIT_CASE(0, FF) BFM_SPLIT_CASE(1, FF) BFM_SPLIT_CASE(2, FF) \
+    BFM_SPLIT_CASE(3, FF) BFM_SPLIT_CASE(4, FF)
+    BFM_SPLIT_F(12) BFM_SPLIT_F(23) BFM_SPLIT_F(24)
+#undef BFM_SPLIT_F
+#undef BFM_SPLIT_CASE
+    return hipErrorInvalidValue;
 }
 
 template <int K, int F, typename T>

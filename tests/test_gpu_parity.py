@@ -63,8 +63,11 @@ def test_config1_latency_tile_full_parity(bfm, orc):
 
 
 def test_lean_and_export_kernels_agree_bitwise(bfm):
+    """The same kernel with and without per-row exports (the time split, which
+    only lean calls take, is pinned to one wave so both run the same kernel)."""
     say("case lean-vs-export seed=2 P=3000 N=228")
     Y = series(3000, 228, 114, seed=2)
+    bfm.tune_set(Y, 1, n=114)
     a = to_numpy(bfm.fit_monitor(Y, n=114, outputs=("brk", "mag", "sigma", "status")))
     b = to_numpy(bfm.fit_monitor(Y, n=114, outputs=ALL))
     for k in a:
