@@ -42,7 +42,18 @@
  *     DEGENERATE_SIGMA (an exact season-trend series has no MOSUM);
  *   - a history design is RANK_DEFICIENT when, with the trend column divided
  *     by n and the columns in the order of Eq. 2, its QR factor has some
- *     |R_jj| <= 1e-6 * sqrt(n_v).
+ *     |R_jj| <= 1e-6 * sqrt(n_v);
+ *   - irregular time (Section 4, the Chile scene): when a vector of
+ *     observation times is given, the design rows of Eq. 2 take the time of
+ *     each observation (there: its day number, f = 365) in place of the index
+ *     t, while the history, the window h, the boundary's t/n and the break
+ *     index stay counts of observations.  The trend column is then divided by
+ *     (t_n - t_1) n / (n - 1), which is n for t = 1..N;
+ *   - filling (the footnote of Section 3): each non-finite observation takes
+ *     the value of the last finite one before it (forward fill); those before
+ *     the first finite one take that one (backward fill).  The filled series
+ *     then goes through the plain path; a series with no finite value is
+ *     INSUFFICIENT.
  *
  * Parity: every function here is pinned by the CPU test suite against closed
  * forms, invariants, LAPACK least squares and brute force.
@@ -58,6 +69,7 @@
 #define BFO_MASK_NONE 0
 #define BFO_MASK_NAN 1
 #define BFO_MASK_EXPLICIT 2
+#define BFO_MASK_FILL 3
 
 #define BFO_OK 0
 #define BFO_NONFINITE 1
@@ -78,10 +90,12 @@ typedef struct {
     int32_t h_window; /* window as a count; overrides h_frac if > 0 */
     double lambda;    /* critical value of the boundary           */
     int32_t mask_mode;
+    const double *times; /* NULL: t = 1..N; else the time of each observation */
 } bfo_params;
 
-/* Eq. 2: one design row, t is the 1-based time index. */
-static void design_row(int t, int k, double f, double *x)
+/* Eq. 2: one design row at time t (the 1-based index, or the observation's
+ * time when times are given). */
+static void design_row(double t, int k, double f, double *x)
 {
     x[0] = 1.0;
     x[1] = (double)t;
@@ -141,6 +155,20 @@ static int householder_lstsq(double *A, double *b, int m, int p, double tscale, 
     return 0;
 }
 
+/* Time of the observation with 1-based index t. */
+static double time_of(const bfo_params *prm, int t)
+{
+    return prm->times ? prm->times[t - 1] : (double)t;
+}
+
+/* Divisor of the trend column in the factorisation: n for t = 1..N. */
+static double trend_scale(const bfo_params *prm)
+{
+    const int n = prm->n_hist;
+    if (!prm->times || n < 2) return (double)n;
+    return (prm->times[n - 1] - prm->times[0]) * (double)n / (double)(n - 1);
+}
+
 typedef struct {
     int32_t *brk;
     double *mag;
@@ -168,6 +196,21 @@ static void pixel(const bfo_params *prm, const float *Y, const double *Yd, int64
 
     for (int t = 0; t < N; ++t)
         y[t] = Yd ? Yd[(int64_t)t * ld + i] : (double)Y[(int64_t)t * ld + i];
+    if (prm->mask_mode == BFO_MASK_FILL) {
+        /* footnote of Section 3: forward fill, then backward fill of the
+         * leading gap from the first finite value */
+        double last = NAN;
+        for (int t = 0; t < N; ++t) {
+            if (isfinite(y[t])) last = y[t];
+            else y[t] = last;
+        }
+        double next = NAN;
+        for (int t = N - 1; t >= 0; --t) {
+            if (isfinite(y[t])) next = y[t];
+            else y[t] = next;
+        }
+        if (N > 0 && !isfinite(y[0])) st = BFO_INSUFFICIENT; /* no finite value at all */
+    }
     if (o->resid)
         for (int t = 0; t < N; ++t) o->resid[(int64_t)t * P + i] = NAN;
     if (o->mosum)
@@ -180,9 +223,9 @@ static void pixel(const bfo_params *prm, const float *Y, const double *Yd, int64
     for (int t = 1; t <= N; ++t) {
         double v = y[t - 1];
         int use;
-        if (prm->mask_mode == BFO_MASK_NONE) {
+        if (prm->mask_mode == BFO_MASK_NONE || prm->mask_mode == BFO_MASK_FILL) {
             use = 1;
-            if (!isfinite(v)) st = BFO_NONFINITE;
+            if (!isfinite(v) && st == BFO_OK) st = BFO_NONFINITE;
         } else if (prm->mask_mode == BFO_MASK_NAN) {
             use = isfinite(v);
         } else {
@@ -200,17 +243,17 @@ static void pixel(const bfo_params *prm, const float *Y, const double *Yd, int64
     if (st == BFO_OK) {
         /* Eq. 5/6: fit on the valid history */
         for (int u = 0; u < nv; ++u) {
-            design_row(tv[u], k, prm->freq, A + (size_t)u * p);
+            design_row(time_of(prm, tv[u]), k, prm->freq, A + (size_t)u * p);
             rhs[u] = y[tv[u] - 1];
         }
-        if (householder_lstsq(A, rhs, nv, p, (double)n, beta) != 0) st = BFO_RANK_DEFICIENT;
+        if (householder_lstsq(A, rhs, nv, p, trend_scale(prm), beta) != 0) st = BFO_RANK_DEFICIENT;
     }
     if (st == BFO_OK) {
         if (o->beta)
             for (int j = 0; j < p; ++j) o->beta[(int64_t)j * P + i] = beta[j];
         /* Eq. 11: residuals of every valid observation */
         for (int u = 0; u < nv_all; ++u) {
-            design_row(tv[u], k, prm->freq, x);
+            design_row(time_of(prm, tv[u]), k, prm->freq, x);
             double yh = 0.0;
             for (int j = 0; j < p; ++j) yh += x[j] * beta[j];
             e[u] = y[tv[u] - 1] - yh;
@@ -267,7 +310,11 @@ static int run(const bfo_params *prm, const float *Y, const double *Yd, int64_t 
     if (!(prm->lambda > 0)) return -1;
     if (prm->h_window <= 0 && !(prm->h_frac > 0 && prm->h_frac <= 1)) return -1;
     if (prm->h_window > prm->n_hist) return -1;
-    if (prm->mask_mode < 0 || prm->mask_mode > 2) return -1;
+    if (prm->mask_mode < 0 || prm->mask_mode > 3) return -1;
+    if (prm->times)
+        for (int t = 0; t < prm->n_obs; ++t)
+            if (!isfinite(prm->times[t]) || (t > 0 && !(prm->times[t] > prm->times[t - 1])))
+                return -1; /* times must be finite and strictly increasing */
     if (prm->mask_mode == BFO_MASK_EXPLICIT && (!valid || ldv < P)) return -1;
     bfo_outputs o = {brk, mag, sigma, status, beta, resid, mosum};
 #ifdef _OPENMP
@@ -314,5 +361,5 @@ int bfo_threads(int nthreads)
 }
 
 /* Eq. 2 and Eq. 4 exposed for the pins. */
-void bfo_design_row(int t, int k, double f, double *x) { design_row(t, k, f, x); }
+void bfo_design_row(double t, int k, double f, double *x) { design_row(t, k, f, x); }
 double bfo_boundary(double lambda, double ratio) { return boundary(lambda, ratio); }

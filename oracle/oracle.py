@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bfm_oracle.c")
 _LIB = os.path.join(_HERE, "libbfm_oracle.so")
 
-MASK_NONE, MASK_NAN, MASK_EXPLICIT = 0, 1, 2
+MASK_NONE, MASK_NAN, MASK_EXPLICIT, MASK_FILL = 0, 1, 2, 3
 OK, NONFINITE, INSUFFICIENT, RANK_DEFICIENT, DEGENERATE_SIGMA, NO_MONITOR = range(6)
 
 
@@ -35,6 +35,7 @@ class _Params(ctypes.Structure):
         ("h_window", ctypes.c_int32),
         ("lambda_", ctypes.c_double),
         ("mask_mode", ctypes.c_int32),
+        ("times", ctypes.c_void_p),
     ]
 
 
@@ -52,7 +53,7 @@ def build(force: bool = False, src: str = _SRC, out: str = _LIB) -> str:
 class Oracle:
     """The oracle library at ``lib_path`` (the built ``bfm_oracle.c`` by default)."""
 
-    MASK_NONE, MASK_NAN, MASK_EXPLICIT = MASK_NONE, MASK_NAN, MASK_EXPLICIT
+    MASK_NONE, MASK_NAN, MASK_EXPLICIT, MASK_FILL = MASK_NONE, MASK_NAN, MASK_EXPLICIT, MASK_FILL
     OK, NONFINITE, INSUFFICIENT = OK, NONFINITE, INSUFFICIENT
     RANK_DEFICIENT, DEGENERATE_SIGMA, NO_MONITOR = RANK_DEFICIENT, DEGENERATE_SIGMA, NO_MONITOR
 
@@ -65,17 +66,17 @@ class Oracle:
         lib.bfo_fit_monitor.restype = ctypes.c_int
         lib.bfo_fit_monitor_f64.argtypes = lib.bfo_fit_monitor.argtypes
         lib.bfo_fit_monitor_f64.restype = ctypes.c_int
-        lib.bfo_design_row.argtypes = [ctypes.c_int, ctypes.c_int, d, vp]
+        lib.bfo_design_row.argtypes = [d, ctypes.c_int, d, vp]
         lib.bfo_boundary.argtypes = [d, d]
         lib.bfo_boundary.restype = d
         lib.bfo_threads.argtypes = [ctypes.c_int]
         lib.bfo_threads.restype = ctypes.c_int
         self.lib = lib
 
-    def design_row(self, t: int, order: int, freq: float) -> np.ndarray:
-        """Eq. 2: x_t for the 1-based time index t."""
+    def design_row(self, t: float, order: int, freq: float) -> np.ndarray:
+        """Eq. 2: x_t at time t (the 1-based index, or an observation's time)."""
         x = np.empty(2 + 2 * order, np.float64)
-        self.lib.bfo_design_row(int(t), int(order), float(freq), _ptr(x))
+        self.lib.bfo_design_row(float(t), int(order), float(freq), _ptr(x))
         return x
 
     def boundary(self, lam: float, ratio: float) -> float:
@@ -87,11 +88,12 @@ class Oracle:
 
     def fit_monitor(self, Y, *, n: int, order: int = 3, freq: float = 23.0, h: float = 0.25,
                     h_window: int = 0, lam: float = 2.5, mask_mode: int = MASK_NONE,
-                    valid=None, threads: int = 1, extras: bool = True) -> dict:
+                    valid=None, times=None, threads: int = 1, extras: bool = True) -> dict:
         """Run the oracle on a time-major series block ``Y`` of shape (N, P).
 
         ``Y`` is used as float32 (the library's input type) unless it is a float64
-        array, in which case the FP64 entry point is used.
+        array, in which case the FP64 entry point is used.  ``times`` (N values,
+        strictly increasing) replaces the index t in the design rows of Eq. 2.
 
         Returns a dict of numpy arrays: ``brk`` (int32, P), ``mag``, ``sigma``
         (float64, P), ``status`` (uint8, P) and, when ``extras``, ``beta`` (p x P),
@@ -101,8 +103,12 @@ class Oracle:
         Y = np.ascontiguousarray(Y, dtype=np.float64 if f64 else np.float32)
         N, P = Y.shape
         p = 2 + 2 * order
+        tv = None
+        if times is not None:
+            tv = np.ascontiguousarray(times, dtype=np.float64)
+            assert tv.shape == (N,)
         prm = _Params(N, n, order, float(freq), float(h), int(h_window), float(lam),
-                      int(mask_mode))
+                      int(mask_mode), _ptr(tv))
         out = {
             "brk": np.empty(P, np.int32),
             "mag": np.empty(P, np.float64),
@@ -141,8 +147,8 @@ def _oracle() -> Oracle:
     return _default
 
 
-def design_row(t: int, order: int, freq: float) -> np.ndarray:
-    """Eq. 2: x_t for the 1-based time index t."""
+def design_row(t: float, order: int, freq: float) -> np.ndarray:
+    """Eq. 2: x_t at time t (the 1-based index, or an observation's time)."""
     return _oracle().design_row(t, order, freq)
 
 

@@ -36,6 +36,13 @@ MUTANTS = [
      "for (int i = j; i < m; ++i) b[i] -= 0.5 * d * A[i * p + j];"),
     ("no rank test", "if (norm <= tol) return -1;", "if (norm <= 0.0) return -1;"),
     ("RSS over the first n_v-1 values", "rss += e[u] * e[u];", "rss += u + 1 < nv ? e[u] * e[u] : 0.0;"),
+    ("times ignored", "return prm->times ? prm->times[t - 1] : (double)t;", "return (double)t;"),
+    ("times one row late", "return prm->times ? prm->times[t - 1] : (double)t;",
+     "return prm->times ? prm->times[t < prm->n_obs ? t : t - 1] : (double)t;"),
+    ("no forward fill", "            else y[t] = last;\n", "            else y[t] = y[t];\n"),
+    ("gap filled from the next value", "            if (isfinite(y[t])) last = y[t];\n            else y[t] = last;",
+     "            if (isfinite(y[t])) last = y[t];\n            else y[t] = t + 1 < N && isfinite(y[t + 1]) ? y[t + 1] : last;"),
+    ("all-missing series not flagged", "if (N > 0 && !isfinite(y[0])) st = BFO_INSUFFICIENT;", "if (0) st = BFO_INSUFFICIENT;"),
 ]
 
 

@@ -368,3 +368,152 @@ def test_threads_do_not_change_results(orc):
     b = orc.fit_monitor(y, n=114, threads=4)
     for k in a:
         np.testing.assert_array_equal(a[k], b[k])
+
+
+# ------------------------------------- irregular time (Section 4, Chile) ----
+def acquisition_days(N, seed=0):
+    """Day numbers of N acquisitions: gaps of 8 to 48 days (revisits of 8 or 16
+    days, some lost to clouds), strictly increasing, starting at day 18."""
+    rng = np.random.default_rng(seed)
+    return 18.0 + np.concatenate([[0.0], np.cumsum(rng.choice([8.0, 16.0, 16.0, 16.0, 32.0, 48.0], N - 1))])
+
+
+def seasonal_in_time(days, P, order=3, seed=0, noise=0.02):
+    rng = np.random.default_rng(seed)
+    t = days[:, None]
+    y = 0.5 + 2e-5 * t + np.zeros((len(days), P))
+    for j in range(1, order + 1):
+        y += rng.uniform(0, 0.2, P) * np.sin(2 * np.pi * j * t / 365.0 + rng.uniform(0, 2 * np.pi, P))
+    return y + rng.normal(0, noise, y.shape)
+
+
+def test_times_equal_to_the_index_give_the_regular_path(orc):
+    """times = 1..N is the regular series: every output identical."""
+    y = noisy(150, 40, seed=30)
+    y[np.random.default_rng(31).random(y.shape) < 0.2] = np.nan
+    idx = np.arange(1, 151, dtype=np.float64)
+    for mode in (orc.MASK_NONE, orc.MASK_NAN):
+        a = orc.fit_monitor(y, n=75, mask_mode=mode)
+        b = orc.fit_monitor(y, n=75, mask_mode=mode, times=idx)
+        for k in a:
+            np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+def test_exact_series_in_irregular_time_recovers_beta(orc):
+    """A noise-free season-trend series in day numbers (f = 365): the fit
+    recovers the coefficients of Eq. 2 that built it."""
+    N, n, k = 288, 144, 3
+    days = acquisition_days(N, seed=32)
+    beta = np.array([0.4, 3e-5, 0.1, -0.05, 0.03, 0.02, -0.01, 0.015])
+    X = np.column_stack([np.ones(N), days] + [f(2 * np.pi * j * days / 365.0)
+                                                for j in range(1, k + 1) for f in (np.sin, np.cos)])
+    y = (X @ beta)[:, None]
+    r = orc.fit_monitor(y, n=n, order=k, freq=365.0, h_window=72, times=days)
+    np.testing.assert_allclose(r["beta"][:, 0], beta, rtol=1e-8, atol=1e-12)
+    np.testing.assert_allclose(r["resid"][:, 0], 0.0, atol=1e-12)
+    assert r["status"][0] == orc.DEGENERATE_SIGMA
+
+
+@pytest.mark.parametrize("shift,scale", [(365.0 * 3, 1.0), (17.3, 1.0), (0.0, 1.0 / 365.0)])
+def test_time_origin_and_unit_do_not_change_the_monitor(orc, shift, scale):
+    """Shifting every time (the trend and harmonic columns span the same space)
+    or changing the unit together with f leaves the fitted values, sigma, the
+    MOSUM and the break unchanged."""
+    N, n = 288, 144
+    days = acquisition_days(N, seed=33)
+    y = seasonal_in_time(days, 30, seed=34)
+    y[200:, ::3] -= 0.2
+    a = orc.fit_monitor(y, n=n, order=3, freq=365.0, h_window=72, times=days)
+    b = orc.fit_monitor(y, n=n, order=3, freq=365.0 * scale, h_window=72,
+                        times=(days + shift) * scale)
+    np.testing.assert_array_equal(a["brk"], b["brk"])
+    for key in ("sigma", "mag", "mosum", "resid"):
+        np.testing.assert_allclose(a[key], b[key], rtol=1e-9, atol=1e-10, err_msg=key)
+    assert (a["brk"][::3] >= 0).all()
+
+
+def test_irregular_time_with_gaps_brute_force(orc):
+    """Dropped observations in irregular time: LAPACK least squares on the
+    valid history at the observations' day numbers, windows summed by brute
+    force, boundary at compacted positions."""
+    N, n, k, H, lam = 288, 144, 3, 72, 2.5
+    days = acquisition_days(N, seed=35)
+    P = 12
+    y = seasonal_in_time(days, P, seed=36)
+    rng = np.random.default_rng(37)
+    miss = rng.random((N, P)) < 0.2
+    y[miss] = np.nan
+    y[220:, ::2] -= 0.15
+    r = orc.fit_monitor(y, n=n, order=k, freq=365.0, h_window=H, lam=lam,
+                        mask_mode=orc.MASK_NAN, times=days)
+    X = np.column_stack([np.ones(N), days] + [f(2 * np.pi * j * days / 365.0)
+                                                for j in range(1, k + 1) for f in (np.sin, np.cos)])
+    for i in range(P):
+        v = np.nonzero(~miss[:, i])[0]
+        vh = v[v < n]
+        nv = len(vh)
+        beta = np.linalg.lstsq(X[vh], y[vh, i], rcond=None)[0]
+        e = y[v, i] - X[v] @ beta
+        sig = math.sqrt((e[:nv] ** 2).sum() / (nv - (2 + 2 * k)))
+        mo = np.array([e[u - H + 1:u + 1].sum() for u in range(nv, len(v))]) / (sig * math.sqrt(nv))
+        np.testing.assert_allclose(r["beta"][:, i], beta, rtol=1e-7, atol=1e-11)
+        assert abs(r["sigma"][i] - sig) < 1e-11
+        np.testing.assert_allclose(r["mosum"][v[nv:] - n, i], mo, atol=1e-9)
+        u1 = np.arange(nv + 1, len(v) + 1) / nv
+        b = lam * np.sqrt(np.where(u1 <= math.e, 1.0, np.log(np.maximum(u1, 1.0))))
+        hit = np.nonzero(np.abs(mo) > b)[0]
+        assert r["brk"][i] == (v[nv + hit[0]] - n if len(hit) else -1)
+    assert (r["brk"][::2] >= 0).all()
+
+
+def test_rejects_times_that_do_not_increase(orc):
+    y = noisy(40, 2, seed=38)
+    t = np.arange(1.0, 41.0)
+    for bad in (t[::-1].copy(), np.where(t == 10, 9.0, t), np.where(t == 5, np.nan, t)):
+        with pytest.raises(ValueError):
+            orc.fit_monitor(y, n=20, times=bad)
+
+
+# ------------------------------------ filling (footnote of Section 3) ----
+def test_fill_is_forward_then_backward_fill(orc):
+    """MASK_FILL equals the plain path on the series filled by pandas (ffill,
+    then bfill for the leading gap), bit for bit."""
+    pd = pytest.importorskip("pandas")
+    N, n, P = 200, 100, 40
+    y = noisy(N, P, seed=39)
+    rng = np.random.default_rng(40)
+    y[rng.random((N, P)) < 0.1] = np.nan
+    for i in range(0, P, 4):                       # runs, leading and trailing gaps
+        a = int(rng.integers(0, N - 10))
+        y[a:a + int(rng.integers(2, 10)), i] = np.nan
+    y[:7, 1] = np.nan
+    y[-5:, 2] = np.nan
+    y[3, 5] = np.inf
+    filled = pd.DataFrame(np.where(np.isfinite(y), y, np.nan)).ffill().bfill().to_numpy()
+    assert np.isfinite(filled).all()
+    a = orc.fit_monitor(y, n=n, mask_mode=orc.MASK_FILL)
+    b = orc.fit_monitor(filled, n=n, mask_mode=orc.MASK_NONE)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+def test_fill_special_cases(orc):
+    N, n = 60, 30
+    y = noisy(N, 4, seed=41)
+    complete = orc.fit_monitor(y, n=n)
+    r = orc.fit_monitor(y, n=n, mask_mode=orc.MASK_FILL)
+    for k in r:                                     # nothing missing: the plain path
+        np.testing.assert_array_equal(r[k], complete[k], err_msg=k)
+    y[:, 1] = np.nan                                # nothing to fill from
+    y[:n, 2] = np.nan                               # history backward-filled: constant
+    y[[0, 1, 2, 40], 3] = np.nan                    # leading gap takes y[3]
+    r = orc.fit_monitor(y, n=n, mask_mode=orc.MASK_FILL)
+    assert r["status"][1] == orc.INSUFFICIENT and r["brk"][1] == -1
+    assert r["status"][2] == orc.DEGENERATE_SIGMA
+    assert r["status"][3] == orc.OK
+    y3 = y[:, 3].copy()
+    y3[:3] = y3[3]
+    y3[40] = y3[39]
+    ref = orc.fit_monitor(y3[:, None], n=n)
+    for k in ref:
+        np.testing.assert_array_equal(r[k][..., 3:4], ref[k], err_msg=k)
