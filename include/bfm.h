@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define BFM_VERSION 2
+#define BFM_VERSION 3
 
 /* return codes */
 #define BFM_SUCCESS 0
@@ -43,12 +43,20 @@ extern "C" {
 #define BFM_E_HIP (-5)         /* a HIP runtime call failed                 */
 #define BFM_E_UNSUPPORTED (-6) /* device is not gfx950, or option not built  */
 
-/* how missing observations are found (missing ones are dropped) */
+/* how missing observations are found and treated (MASK_NAN and
+ * MASK_EXPLICIT drop them; MASK_FILL fills them) */
 #define BFM_MASK_NONE 0     /* every observation is used; a non-finite one
                                makes the pixel BFM_ST_NONFINITE            */
 #define BFM_MASK_NAN 1      /* an observation is used iff it is finite      */
 #define BFM_MASK_EXPLICIT 2 /* used iff valid[t*ldv+i] != 0; a non-finite
                                used observation makes the pixel NONFINITE  */
+#define BFM_MASK_FILL 3     /* the footnote of Section 3: a non-finite
+                               observation takes the value of the last
+                               finite one before it, those before the first
+                               finite one take that one, and the filled
+                               series goes through the plain path; a series
+                               with no finite value is BFM_ST_INSUFFICIENT.
+                               float32 series, order <= 8                  */
 
 /* arithmetic of the computation */
 #define BFM_PREC_FP64 0
@@ -84,6 +92,15 @@ extern "C" {
  *   lambda    critical value of the boundary (Eq. 4), > 0.
  *   mask_mode one of BFM_MASK_*.
  *   precision BFM_PREC_FP64.
+ *   times     host, NULL or N doubles, finite and strictly increasing: the
+ *             time of each observation, used in place of the index t in the
+ *             design rows of Eq. 2 (Section 4 does this with day numbers and
+ *             f = 365 for an unevenly sampled scene).  The history, the window
+ *             and the boundary's t/n stay counts of observations, and brk
+ *             stays an observation index.  Read during the call (for a server
+ *             request: until the request completes); the library keeps a copy
+ *             of the operators built from it.  Parameter sets with times take
+ *             the table-driven kernels (float32 series only).
  */
 typedef struct {
     int32_t n_obs;
@@ -95,6 +112,7 @@ typedef struct {
     double lambda;
     int32_t mask_mode;
     int32_t precision;
+    const double *times;
 } bfm_params;
 
 /*
@@ -183,8 +201,9 @@ int bfm_fit_monitor(bfm_ctx *ctx, const bfm_params *prm, const float *Y, int64_t
  * ld and ldv count elements.  16-bit series are served by the period-blocked
  * kernels: f in {12, 23, 24} and order <= 4, and additionally on the plain path
  * a window H >= f, a full-rank history design and ld * 2 * f < 2^31, on the
- * missing-value paths n_hist <= 8192 and ld * 4 * f < 2^31; other parameter
- * sets return BFM_E_UNSUPPORTED.
+ * missing-value paths n_hist <= 8192 and ld * 4 * f < 2^31, and neither
+ * observation times nor BFM_MASK_FILL; other parameter sets return
+ * BFM_E_UNSUPPORTED.
  * Errors: those of bfm_fit_monitor, BFM_E_INVAL for an unknown y_dtype, and
  * BFM_E_UNSUPPORTED as above.
  */
@@ -237,8 +256,9 @@ typedef struct bfm_server bfm_server;
 
 /*
  * A request: the arguments of bfm_fit_monitor_typed without the outputs.  Y
- * (and valid) are caller-owned device memory that must stay unchanged until the
- * request completes.  `outputs` selects the arrays the server allocates in its
+ * (and valid) are caller-owned device memory, and prm.times (if not NULL)
+ * caller-owned host memory, that must stay unchanged until the request
+ * completes.  `outputs` selects the arrays the server allocates in its
  * pool, in element type out_dtype (BFM_OUT_F32 or BFM_OUT_F64).
  */
 typedef struct {

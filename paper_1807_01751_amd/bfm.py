@@ -12,6 +12,7 @@ import ctypes
 import os
 import threading
 
+import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -20,7 +21,7 @@ LIB_PATH = os.path.join(_PKG, "libbfm.so")
 # include/bfm.h constants
 SUCCESS = 0
 E_INVAL, E_LAYOUT, E_NOMEM, E_NODEVICE, E_HIP, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
-MASK_NONE, MASK_NAN, MASK_EXPLICIT = 0, 1, 2
+MASK_NONE, MASK_NAN, MASK_EXPLICIT, MASK_FILL = 0, 1, 2, 3
 PREC_FP64 = 0
 Y_F32, Y_BF16, Y_F16 = 0, 1, 2
 _Y_DTYPES = {torch.float32: Y_F32, torch.bfloat16: Y_BF16, torch.float16: Y_F16}
@@ -56,6 +57,7 @@ class Params(ctypes.Structure):
         ("lambda_", ctypes.c_double),
         ("mask_mode", ctypes.c_int32),
         ("precision", ctypes.c_int32),
+        ("times", ctypes.c_void_p),
     ]
 
 
@@ -152,9 +154,20 @@ def version() -> int:
 
 
 def make_params(N: int, n: int, order: int = 3, freq: float = 23.0, h: float = 0.25,
-                h_window: int = 0, lam: float = 2.5, mask_mode: int = MASK_NONE) -> Params:
-    return Params(int(N), int(n), int(order), int(h_window), float(freq), float(h), float(lam),
-                  int(mask_mode), PREC_FP64)
+                h_window: int = 0, lam: float = 2.5, mask_mode: int = MASK_NONE,
+                times=None) -> Params:
+    """bfm_params.  ``times`` (N observation times, host) is copied into a
+    float64 array that the returned struct keeps alive."""
+    keep = None
+    if times is not None:
+        keep = np.ascontiguousarray(np.asarray(times, dtype=np.float64))
+        if keep.shape != (int(N),):
+            raise ValueError(f"times must hold N = {N} values")
+    prm = Params(int(N), int(n), int(order), int(h_window), float(freq), float(h), float(lam),
+                 int(mask_mode), PREC_FP64,
+                 None if keep is None else keep.ctypes.data_as(ctypes.c_void_p))
+    prm._times = keep
+    return prm
 
 
 def check_params(prm: Params, P: int, ld: int) -> None:
@@ -208,7 +221,7 @@ def _series_layout(Y: torch.Tensor):
 
 def fit_monitor(Y: torch.Tensor, *, n: int, order: int = 3, freq: float = 23.0, h: float = 0.25,
                 h_window: int = 0, lam: float = 2.5, mask_mode: int = MASK_NONE,
-                valid: torch.Tensor | None = None, outputs=("brk", "mag"),
+                valid: torch.Tensor | None = None, times=None, outputs=("brk", "mag"),
                 out_dtype: torch.dtype = torch.float64, out: dict | None = None,
                 stream: torch.cuda.Stream | None = None) -> dict:
     """bfm_fit_monitor on a device-resident series block (float32, bfloat16 or
@@ -217,14 +230,15 @@ def fit_monitor(Y: torch.Tensor, *, n: int, order: int = 3, freq: float = 23.0, 
     ``Y`` is time-major: shape (N, P) with unit stride along pixels (or the
     (P, N) transpose view of such a block).  ``outputs`` names the arrays to
     produce among brk, mag, sigma, status, beta, resid, mosum; ``out`` may supply
-    preallocated tensors for them.  Work is enqueued on ``stream`` (default: the
+    preallocated tensors for them.  ``times`` (N observation times, host) replaces
+    the index t in the design rows.  Work is enqueued on ``stream`` (default: the
     current stream) and the call returns without synchronising.
     """
     if Y.dtype not in _Y_DTYPES or Y.device.type != "cuda":
         raise ValueError("Y must be a float32, bfloat16 or float16 tensor on a HIP device")
     Y, N, P, ld = _series_layout(Y)
     dev = Y.device.index if Y.device.index is not None else torch.cuda.current_device()
-    prm = make_params(N, n, order, freq, h, h_window, lam, mask_mode)
+    prm = make_params(N, n, order, freq, h, h_window, lam, mask_mode, times)
     p = 2 + 2 * order
     shapes = {"brk": ((P,), torch.int32), "mag": ((P,), out_dtype), "sigma": ((P,), out_dtype),
               "status": ((P,), torch.uint8), "beta": ((p, P), out_dtype),
@@ -321,13 +335,14 @@ class Server:
             pass
 
     def request(self, Y, *, n, order=3, freq=23.0, h=0.25, h_window=0, lam=2.5,
-                mask_mode=MASK_NONE, valid=None, outputs=("brk", "mag"),
+                mask_mode=MASK_NONE, valid=None, times=None, outputs=("brk", "mag"),
                 out_dtype=torch.float64):
-        """The bfm_request for these arguments (no device work)."""
+        """The bfm_request for these arguments (no device work).  The request
+        keeps its observation times alive."""
         if Y.dtype not in _Y_DTYPES or Y.device.type != "cuda":
             raise ValueError("Y must be a float32, bfloat16 or float16 tensor on a HIP device")
         Y, N, P, ld = _series_layout(Y)
-        prm = make_params(N, n, order, freq, h, h_window, lam, mask_mode)
+        prm = make_params(N, n, order, freq, h, h_window, lam, mask_mode, times)
         want = 0
         for name in outputs:
             if name != "brk":
@@ -338,8 +353,10 @@ class Server:
                 raise ValueError("valid is required with MASK_EXPLICIT")
             valid, _, _, ldv = _series_layout(valid)
             vptr = valid.data_ptr()
-        return Request(prm, Y.data_ptr(), _Y_DTYPES[Y.dtype], P, ld, vptr, ldv, want,
-                       OUT_F64 if out_dtype == torch.float64 else OUT_F32)
+        req = Request(prm, Y.data_ptr(), _Y_DTYPES[Y.dtype], P, ld, vptr, ldv, want,
+                      OUT_F64 if out_dtype == torch.float64 else OUT_F32)
+        req._times = prm._times
+        return req
 
     def submit(self, Y, **kw) -> int:
         req = self.request(Y, **kw)

@@ -10,6 +10,8 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <type_traits>
+#include <vector>
 
 #include "bfm_internal.hpp"
 
@@ -23,8 +25,10 @@ struct bfm_ctx {
         double* dev = nullptr;  // q | w | bnd | bmap
         bfm::PeriodicOps per;   // per.F == 0: the period-blocked kernel does not apply
         double* pdev = nullptr; // rt | ri | hh | wh | bnd
+        std::vector<double> times;  // observation times the operators were built for
     };
-    using Key = std::tuple<int, int, int, int, double, double, double>;
+    // (N, n, k, h_window, f, h_frac, lambda, hash of the observation times or 0)
+    using Key = std::tuple<int, int, int, int, double, double, double, uint64_t>;
     std::map<Key, Entry> plain;
     // Autotuned time split of the period-blocked plain kernel, per tile shape:
     // (order, F, H, N, n, y_dtype, ceil(log2(waves))) -> waves per 64 pixels.
@@ -33,6 +37,7 @@ struct bfm_ctx {
     struct MEntry {
         bfm::MaskedOps ops;
         double* dev = nullptr;  // x | g | ph
+        std::vector<double> times;
     };
     std::map<Key, MEntry> masked;
 };
@@ -76,8 +81,12 @@ int check(const bfm_params* prm, int64_t P, int64_t ld)
         return fail(BFM_E_INVAL, "h_window must be in [0, n_hist] (got %d)", p.h_window);
     if (p.h_window == 0 && !(p.h_frac > 0 && p.h_frac <= 1))
         return fail(BFM_E_INVAL, "h_frac must be in (0, 1] when h_window is 0");
-    if (p.mask_mode < BFM_MASK_NONE || p.mask_mode > BFM_MASK_EXPLICIT)
+    if (p.mask_mode < BFM_MASK_NONE || p.mask_mode > BFM_MASK_FILL)
         return fail(BFM_E_INVAL, "unknown mask_mode %d", p.mask_mode);
+    if (p.times)
+        for (int t = 0; t < p.n_obs; ++t)
+            if (!std::isfinite(p.times[t]) || (t > 0 && !(p.times[t] > p.times[t - 1])))
+                return fail(BFM_E_INVAL, "times must be finite and strictly increasing (index %d)", t);
     if (p.precision != BFM_PREC_FP64)
         return fail(BFM_E_INVAL, "unknown precision %d", p.precision);
     if (P < 0) return fail(BFM_E_INVAL, "P must be >= 0");
@@ -132,14 +141,47 @@ int choose_split(bfm_ctx* ctx, const bfm_params& p, int y_dtype, int64_t P, int 
     return 1;
 }
 
+// FNV-1a over the bytes of the observation times (0: index time).
+uint64_t times_hash(const bfm_params& p)
+{
+    if (!p.times) return 0;
+    uint64_t h = 1469598103934665603ull;
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(p.times);
+    for (size_t i = 0; i < (size_t)p.n_obs * sizeof(double); ++i) h = (h ^ b[i]) * 1099511628211ull;
+    return h | 1;
+}
+
+std::vector<double> times_of(const bfm_params& p)
+{
+    return p.times ? std::vector<double>(p.times, p.times + p.n_obs) : std::vector<double>();
+}
+
+// A cached entry built for other observation times under the same hash is
+// dropped (its device block freed) so that it is rebuilt.
+template <typename Map>
+void drop_if_stale(Map& m, const bfm_ctx::Key& key, const bfm_params& p)
+{
+    auto it = m.find(key);
+    if (it == m.end() || !p.times) return;
+    if (it->second.times.size() == (size_t)p.n_obs &&
+        std::memcmp(it->second.times.data(), p.times, (size_t)p.n_obs * sizeof(double)) == 0)
+        return;
+    (void)hipFree(it->second.dev);
+    if constexpr (std::is_same_v<typename Map::mapped_type, bfm_ctx::Entry>)
+        if (it->second.pdev) (void)hipFree(it->second.pdev);
+    m.erase(it);
+}
+
 // The plain-path operators of a parameter set (built and copied to the device
 // on first use).  Call with ctx->mu held.
 int plain_entry(bfm_ctx* ctx, const bfm_params& p, bfm_ctx::Entry** out)
 {
-    bfm_ctx::Key key{p.n_obs, p.n_hist, p.order, p.h_window, p.freq, p.h_frac, p.lambda};
+    bfm_ctx::Key key{p.n_obs, p.n_hist, p.order, p.h_window, p.freq, p.h_frac, p.lambda, times_hash(p)};
+    drop_if_stale(ctx->plain, key, p);
     auto it = ctx->plain.find(key);
     if (it == ctx->plain.end()) {
         bfm_ctx::Entry ent;
+        ent.times = times_of(p);
         bfm::build_plain_ops(p, &ent.ops);
         const size_t nq = ent.ops.q.size(), nw = ent.ops.w.size(), nb = ent.ops.bnd.size(),
                      nm = ent.ops.bmap.size();
@@ -185,10 +227,12 @@ int plain_entry(bfm_ctx* ctx, const bfm_params& p, bfm_ctx::Entry** out)
 int fit_masked(bfm_ctx* ctx, const bfm_params& p, const void* Y, int y_dtype, int64_t P, int64_t ld,
                const uint8_t* valid, int64_t ldv, const bfm_outputs& out, hipStream_t s)
 {
-    bfm_ctx::Key key{p.n_obs, p.n_hist, p.order, p.h_window, p.freq, p.h_frac, 0.0};
+    bfm_ctx::Key key{p.n_obs, p.n_hist, p.order, p.h_window, p.freq, p.h_frac, 0.0, times_hash(p)};
+    drop_if_stale(ctx->masked, key, p);
     auto it = ctx->masked.find(key);
     if (it == ctx->masked.end()) {
         bfm_ctx::MEntry ent;
+        ent.times = times_of(p);
         bfm::build_masked_ops(p, &ent.ops);
         std::vector<double> host(ent.ops.x);
         host.insert(host.end(), ent.ops.g.begin(), ent.ops.g.end());
@@ -231,6 +275,8 @@ int fit_masked(bfm_ctx* ctx, const bfm_params& p, const void* Y, int y_dtype, in
     a.cap = ops.cap;
     a.h_frac = p.h_frac;
     a.lambda = p.lambda;
+    a.tc = ops.tc;
+    a.ts = ops.ts;
     a.brk = out.brk;
     a.mag = out.mag;
     a.sigma = out.sigma;
@@ -337,22 +383,23 @@ int bfm_fit_monitor_typed(bfm_ctx* ctx, const bfm_params* prm, const void* Y, in
         if (!valid) return fail(BFM_E_INVAL, "valid is required with BFM_MASK_EXPLICIT");
         if (ldv < P) return fail(BFM_E_LAYOUT, "ldv must be >= P");
     }
-    if (prm->mask_mode != BFM_MASK_NONE && prm->order > bfm::kMaskedMaxOrder)
+    const bool fill = prm->mask_mode == BFM_MASK_FILL;
+    const bool masked = prm->mask_mode == BFM_MASK_NAN || prm->mask_mode == BFM_MASK_EXPLICIT;
+    if (masked && prm->order > bfm::kMaskedMaxOrder)
         return fail(BFM_E_UNSUPPORTED, "missing-value modes support order <= %d (got %d)",
                     bfm::kMaskedMaxOrder, prm->order);
+    if (fill && narrow) return fail(BFM_E_UNSUPPORTED, "BFM_MASK_FILL takes float32 series");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bfm_params& p = *prm;
     const int np = 2 + 2 * p.order;
 
     std::lock_guard<std::mutex> lock(ctx->mu);
     DeviceGuard g(ctx->device);
-    if (p.mask_mode != BFM_MASK_NONE) return fit_masked(ctx, p, Y, y_dtype, P, ld, valid, ldv, *out, s);
+    if (masked) return fit_masked(ctx, p, Y, y_dtype, P, ld, valid, ldv, *out, s);
     bfm_ctx::Entry* ent = nullptr;
     rc = plain_entry(ctx, p, &ent);
     if (rc) return rc;
-    auto* it = &*ctx->plain.find(bfm_ctx::Key{p.n_obs, p.n_hist, p.order, p.h_window, p.freq, p.h_frac,
-                                               p.lambda});
-    const bfm::PlainOps& ops = it->second.ops;
+    const bfm::PlainOps& ops = ent->ops;
 
     uint8_t global_st = BFM_ST_OK;
     if (ops.n <= ops.p || ops.H < 1)
@@ -371,16 +418,17 @@ int bfm_fit_monitor_typed(bfm_ctx* ctx, const bfm_params* prm, const void* Y, in
                     ops.H, lds, ctx->max_lds);
     // The period-blocked kernel addresses the F rows of a block with 32-bit offsets.
     const int64_t esize = y_dtype == BFM_Y_F32 ? 4 : 2;
-    if (it->second.per.F > 0 && ld * esize * it->second.per.F < ((int64_t)1 << 31)) {
+    if (ent->per.F > 0 && ld * esize * ent->per.F < ((int64_t)1 << 31)) {
         bfm::PeriodicArgs a{};
         a.Y = Y;
         a.y_dtype = y_dtype;
-        a.split = y_dtype == BFM_Y_F32 && !out->resid && !out->mosum
-                      ? choose_split(ctx, p, y_dtype, P, ops.H, it->second.per.F)
+        a.fill = fill;
+        a.split = y_dtype == BFM_Y_F32 && !fill && !out->resid && !out->mosum
+                      ? choose_split(ctx, p, y_dtype, P, ops.H, ent->per.F)
                       : 1;
         a.ld = ld;
         a.P = P;
-        a.tab = it->second.pdev;
+        a.tab = ent->pdev;
         a.N = p.n_obs;
         a.n = p.n_hist;
         a.H = ops.H;
@@ -396,14 +444,14 @@ int bfm_fit_monitor_typed(bfm_ctx* ctx, const bfm_params* prm, const void* Y, in
         a.resid = out->resid;
         a.mosum = out->mosum;
         a.out_f64 = out->out_dtype == BFM_OUT_F64;
-        e = bfm::launch_periodic(a, p.order, it->second.per.F, s);
+        e = bfm::launch_periodic(a, p.order, ent->per.F, s);
         if (e != hipSuccess) return hip_fail(e, "periodic kernel launch");
         return BFM_SUCCESS;
     }
     if (narrow)
         return fail(BFM_E_UNSUPPORTED, "a 16-bit series needs f in {12, 23, 24}, order <= %d, a "
                     "window H >= f and ld * 2 * f < 2^31 on this path", bfm::kPeriodicMaxOrder);
-    const double* d = it->second.dev;
+    const double* d = ent->dev;
     const size_t nq = ops.q.size(), nw = ops.w.size(), nb = ops.bnd.size();
     bfm::PlainArgs a{};
     a.Y = static_cast<const float*>(Y);
@@ -420,6 +468,7 @@ int bfm_fit_monitor_typed(bfm_ctx* ctx, const bfm_params* prm, const void* Y, in
     a.lambda = p.lambda;
     a.sqrt_n = std::sqrt((double)p.n_hist);
     a.inv_dof = 1.0 / (double)(p.n_hist - np);
+    a.fill = fill;
     a.brk = out->brk;
     a.mag = out->mag;
     a.sigma = out->sigma;
@@ -445,7 +494,8 @@ int split_shape(bfm_ctx* ctx, const bfm_params* prm, int32_t y_dtype, int64_t P,
     if (y_dtype != BFM_Y_F32 && y_dtype != BFM_Y_BF16 && y_dtype != BFM_Y_F16)
         return fail(BFM_E_INVAL, "unknown y_dtype %d", y_dtype);
     if (prm->mask_mode != BFM_MASK_NONE || y_dtype != BFM_Y_F32)
-        return fail(BFM_E_UNSUPPORTED, "tile tuning applies to the plain path on float32 series");
+        return fail(BFM_E_UNSUPPORTED, "tile tuning applies to the plain path (no missing-value "
+                    "handling) on float32 series");
     std::lock_guard<std::mutex> lock(ctx->mu);
     DeviceGuard g(ctx->device);
     bfm_ctx::Entry* ent = nullptr;

@@ -56,6 +56,7 @@ void build_periodic_ops(const bfm_params& prm, const PlainOps& ops, int F, Perio
 constexpr int kMaskedMaxOrder = 4;  // per-pixel Gram and Cholesky held in VGPRs
 struct MaskedOps {
     int N = 0, n = 0, p = 0, ng = 0, Hmax = 0, cap = 0;
+    double tc = 0, ts = 1;  // trend column tau = (t - tc) / ts
     std::vector<double> x;  // N x p: x~_t
     std::vector<double> g;  // n x ng: tau, tau^2, sin(m w t), cos(m w t) for m = 1..2k,
                             // tau sin(j w t), tau cos(j w t) for j = 1..k
@@ -71,6 +72,10 @@ struct MaskedOps {
 // 16-bit field of its window ring).
 constexpr int kMaskedPeriodicMaxHist = 8192;
 bool build_masked_ops(const bfm_params& prm, MaskedOps* ops);
+
+// Centre and scale of the trend column of the design (tau = (t - tc) / ts):
+// (n+1)/2 and n for t = 1..N, else from the first and last history times.
+void trend_frame(const bfm_params& prm, double* tc, double* ts);
 
 // Window length H for a history of `count` used observations.
 int window_length(const bfm_params& prm, int count);
@@ -92,6 +97,7 @@ struct PlainArgs {
     double lambda;
     double sqrt_n;       // sqrt(n): MOSUM normaliser of Eq. 3
     double inv_dof;      // 1 / (n - p): Algorithm 1, step 5
+    int fill;            // BFM_MASK_FILL: fill missing observations as they are read
     int32_t* brk;
     void* mag;
     void* sigma;
@@ -109,6 +115,7 @@ struct PeriodicArgs {
     const void* Y;       // element type y_dtype (BFM_Y_*)
     int y_dtype;
     int split;           // waves per 64 pixels that share the rows: 1, 2, 4 or 8
+    int fill;            // BFM_MASK_FILL (float32 series, split 1)
     int64_t ld;
     int64_t P;
     const double* tab;   // rt | ri | hh | wh | bnd
@@ -133,6 +140,7 @@ hipError_t launch_periodic_split4(const PeriodicArgs& a, int order, int F, hipSt
 hipError_t launch_periodic_split8(const PeriodicArgs& a, int order, int F, hipStream_t stream);
 hipError_t launch_periodic_bf16(const PeriodicArgs& a, int order, int F, hipStream_t stream);
 hipError_t launch_periodic_f16(const PeriodicArgs& a, int order, int F, hipStream_t stream);
+hipError_t launch_periodic_fill(const PeriodicArgs& a, int order, int F, hipStream_t stream);
 
 // Arguments of the masked kernel (by value; every pointer is device memory).
 struct MaskedArgs {
@@ -148,6 +156,7 @@ struct MaskedArgs {
     int F;                 // 0: general kernel
     int N, n, h_window, cap;
     double h_frac, lambda;
+    double tc, ts;         // time centre and scale of the trend column: tau = (t - tc) / ts
     int32_t* brk;
     void* mag;
     void* sigma;

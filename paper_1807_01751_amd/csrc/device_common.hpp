@@ -289,5 +289,32 @@ __device__ __forceinline__ void stream_aligned(Cursor cur, int t0, int t1, Body&
     }
 }
 
+// Filling of missing observations (the footnote of Section 3): a non-finite
+// observation takes the last finite one before it, and those before a lane's
+// first finite observation take that one.  first_finite scans rows from the
+// top until every lane of the wave has found its first finite value (the loop
+// is wave-uniform; a lane with none keeps a NaN); Filler then fills each row
+// as it is consumed, in time order.
+template <typename T>
+__device__ __forceinline__ float first_finite(const T* __restrict__ Y, int64_t ld, uint32_t lane, int N)
+{
+    float v = to_float(Y[lane]);
+    for (int t = 1; t < N && __ballot(!__builtin_isfinite(v)) != 0; ++t) {
+        const float w = to_float(Y[(int64_t)t * ld + lane]);
+        v = __builtin_isfinite(v) ? v : w;
+    }
+    return v;
+}
+
+struct Filler {
+    float last;
+    __device__ __forceinline__ float operator()(float v)
+    {
+        v = __builtin_isfinite(v) ? v : last;
+        last = v;
+        return v;
+    }
+};
+
 }  // namespace dev
 }  // namespace bfm

@@ -5,9 +5,11 @@
 // per-pixel fit collapses to one contraction with Y (Eq. 8).  This file builds
 // the orthonormal form of that operator once per parameter set:
 //
-//   x~_t  design row of Eq. 2 with the trend written (t - (n+1)/2) / n, which
+//   x~_t  design row of Eq. 2 with the trend written (t - tc) / ts, which
 //         spans the same column space as (1, t) and keeps the factorisation
-//         well conditioned;
+//         well conditioned (tc = (n+1)/2, ts = n for t = 1..N; with
+//         observation times, the same frame from the history's first and last
+//         times);
 //   X~_n = Q R (Householder, rows t = 1..n).  For history rows q_t is row t
 //         of the explicitly formed Q (orthonormal to rounding whatever the
 //         conditioning); for monitoring rows q_t = R^-T x~_t, the same map
@@ -30,14 +32,35 @@ int window_length(const bfm_params& prm, int count)
     return (int)std::floor(prm.h_frac * (double)count);
 }
 
-// Design row of Eq. 2 in the centred-trend basis, 1-based time t.  The angle is
+// Time of the observation with 1-based index t: the index itself, or the
+// given observation time (Section 4 uses day numbers for an unevenly sampled
+// series).  Windows, the history and the boundary stay counts of observations.
+static double time_at(const bfm_params& prm, int t)
+{
+    return prm.times ? prm.times[t - 1] : (double)t;
+}
+
+void trend_frame(const bfm_params& prm, double* tc, double* ts)
+{
+    const int n = prm.n_hist;
+    if (!prm.times) {
+        *tc = 0.5 * (double)(n + 1);
+        *ts = (double)n;
+        return;
+    }
+    const double t1 = prm.times[0], tn = prm.times[n - 1];
+    *tc = 0.5 * (t1 + tn);
+    *ts = n > 1 ? (tn - t1) * (double)n / (double)(n - 1) : 1.0;
+}
+
+// Design row of Eq. 2 in the centred-trend basis at time t.  The angle is
 // reduced exactly (fmod is exact in IEEE arithmetic) before scaling by 2 pi/f.
-static void design_row_centred(int t, int n, int k, double f, double* x)
+static void design_row_centred(double t, double tc, double ts, int k, double f, double* x)
 {
     x[0] = 1.0;
-    x[1] = ((double)t - 0.5 * (double)(n + 1)) / (double)n;
+    x[1] = (t - tc) / ts;
     for (int j = 1; j <= k; ++j) {
-        double ang = (2.0 * M_PI / f) * std::fmod((double)j * (double)t, f);
+        double ang = (2.0 * M_PI / f) * std::fmod((double)j * t, f);
         x[2 * j] = std::sin(ang);
         x[2 * j + 1] = std::cos(ang);
     }
@@ -65,11 +88,13 @@ bool build_plain_ops(const bfm_params& prm, PlainOps* ops)
     // log+ is exactly 1 up to t/n = e, and t/n increases with m.
     while (ops->m_flat < M && (double)(n + 1 + ops->m_flat) / (double)n <= M_E) ++ops->m_flat;
     if (n <= p) return true;  // every pixel INSUFFICIENT; no factorisation
+    double tc, ts;
+    trend_frame(prm, &tc, &ts);
 
     // Householder QR of X~_n (n x p, column-major copy).
     std::vector<double> A((size_t)n * p), x(p);
     for (int t = 1; t <= n; ++t) {
-        design_row_centred(t, n, k, prm.freq, x.data());
+        design_row_centred(time_at(prm, t), tc, ts, k, prm.freq, x.data());
         for (int j = 0; j < p; ++j) A[(size_t)j * n + (t - 1)] = x[j];
     }
     std::vector<double> R((size_t)p * p, 0.0);
@@ -121,7 +146,7 @@ bool build_plain_ops(const bfm_params& prm, PlainOps* ops)
     }
     // Monitoring rows: q_t = R^-T x~_t (forward substitution with R').
     for (int t = n + 1; t <= N; ++t) {
-        design_row_centred(t, n, k, prm.freq, x.data());
+        design_row_centred(time_at(prm, t), tc, ts, k, prm.freq, x.data());
         double* qt = &ops->q[(size_t)(t - 1) * p];
         for (int j = 0; j < p; ++j) {
             double s = x[j];
@@ -145,18 +170,17 @@ bool build_plain_ops(const bfm_params& prm, PlainOps* ops)
             Ri[(size_t)j * p + c] = s / R[(size_t)j * p + j];
         }
     }
-    const double tc = 0.5 * (double)(n + 1);
     for (int c = 0; c < p; ++c) {
         for (int j = 0; j < p; ++j) ops->bmap[(size_t)j * p + c] = Ri[(size_t)j * p + c];
-        ops->bmap[0 * p + c] = Ri[0 * p + c] - (tc / (double)n) * Ri[1 * p + c];
-        ops->bmap[1 * p + c] = Ri[1 * p + c] / (double)n;
+        ops->bmap[0 * p + c] = Ri[0 * p + c] - (tc / ts) * Ri[1 * p + c];
+        ops->bmap[1 * p + c] = Ri[1 * p + c] / ts;
     }
     return true;
 }
 
 int periodic_period(const bfm_params& prm, const PlainOps& ops)
 {
-    if (!ops.rank_ok || ops.n <= ops.p || prm.order > kPeriodicMaxOrder) return 0;
+    if (prm.times || !ops.rank_ok || ops.n <= ops.p || prm.order > kPeriodicMaxOrder) return 0;
     for (int F : kPeriods)
         if (prm.freq == (double)F && ops.H >= F) return F;
     return 0;
@@ -216,18 +240,20 @@ bool build_masked_ops(const bfm_params& prm, MaskedOps* ops)
     ops->cap = (ops->Hmax > 0 ? ops->Hmax : 0) + 1;
     ops->x.assign((size_t)N * p, 0.0);
     ops->g.assign((size_t)n * ng, 0.0);
+    trend_frame(prm, &ops->tc, &ops->ts);
     std::vector<double> x(p);
     for (int t = 1; t <= N; ++t) {
-        design_row_centred(t, n, k, prm.freq, x.data());
+        design_row_centred(time_at(prm, t), ops->tc, ops->ts, k, prm.freq, x.data());
         for (int j = 0; j < p; ++j) ops->x[(size_t)(t - 1) * p + j] = x[j];
     }
     for (int t = 1; t <= n; ++t) {
         double* gr = &ops->g[(size_t)(t - 1) * ng];
-        const double tau = ((double)t - 0.5 * (double)(n + 1)) / (double)n;
+        const double tv = time_at(prm, t);
+        const double tau = (tv - ops->tc) / ops->ts;
         gr[0] = tau;
         gr[1] = tau * tau;
         for (int m = 1; m <= 2 * k; ++m) {
-            double ang = (2.0 * M_PI / prm.freq) * std::fmod((double)m * (double)t, prm.freq);
+            double ang = (2.0 * M_PI / prm.freq) * std::fmod((double)m * tv, prm.freq);
             gr[1 + m] = std::sin(ang);
             gr[1 + 2 * k + m] = std::cos(ang);
         }
@@ -238,7 +264,7 @@ bool build_masked_ops(const bfm_params& prm, MaskedOps* ops)
     }
     ops->F = 0;
     ops->ph.clear();
-    if (k <= kMaskedMaxOrder && n <= kMaskedPeriodicMaxHist)
+    if (!prm.times && k <= kMaskedMaxOrder && n <= kMaskedPeriodicMaxHist)
         for (int F : kPeriods)
             if (prm.freq == (double)F) ops->F = F;
     if (ops->F > 0) {

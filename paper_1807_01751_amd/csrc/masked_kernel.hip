@@ -201,12 +201,12 @@ __global__ __launch_bounds__(kMaskedBlock) void masked_kernel(MaskedArgs a)
     if (a.sigma) put_out(a.sigma, pix, have_fit ? sig : qnan, a.out_f64);
     if (a.beta) {
         // beta~ is in the centred-trend basis of the centred series; map it to
-        // the basis of Eq. 2: tau = (t - (n+1)/2)/n.
-        const double tc = 0.5 * (double)(n + 1);
+        // the basis of Eq. 2: tau = (t - tc)/ts (tc = (n+1)/2, ts = n for
+        // t = 1..N; from the history's first and last times otherwise).
         for (int j = 0; j < NP; ++j) {
             double v = beta[j];
-            if (j == 0) v = beta[0] - (tc / (double)n) * beta[1] + c;
-            if (j == 1) v = beta[1] / (double)n;
+            if (j == 0) v = beta[0] - (a.tc / a.ts) * beta[1] + c;
+            if (j == 1) v = beta[1] / a.ts;
             put_out(a.beta, (int64_t)j * a.P + pix, have_fit ? v : qnan, a.out_f64);
         }
     }

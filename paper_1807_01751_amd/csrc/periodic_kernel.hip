@@ -24,6 +24,7 @@ hipError_t launch_periodic(const PeriodicArgs& a, int order, int F, hipStream_t 
 {
     if (a.y_dtype == BFM_Y_BF16) return launch_periodic_bf16(a, order, F, stream);
     if (a.y_dtype == BFM_Y_F16) return launch_periodic_f16(a, order, F, stream);
+    if (a.fill) return launch_periodic_fill(a, order, F, stream);
     if (a.split > 1 && !a.resid && !a.mosum) return launch_periodic_split(a, order, F, stream);
     return launch_t<float>(a, order, F, stream);
 }

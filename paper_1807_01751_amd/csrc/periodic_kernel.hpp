@@ -17,7 +17,9 @@
 //
 // Rows are processed in blocks aligned to multiples of F so that a row's phase
 // is a compile-time register index.  The series may be stored as float32, BF16
-// or FP16 (template parameter T); arithmetic is FP64 either way.
+// or FP16 (template parameter T); arithmetic is FP64 either way.  With FILL,
+// missing (non-finite) observations are filled forward (backward for a leading
+// gap) as the rows are consumed, and the filled series is monitored.
 //
 // This header holds the kernel template; periodic_kernel.hip (float32) and
 // periodic_kernel_bf16.hip, periodic_kernel_f16.hip and periodic_split_*.hip
@@ -35,7 +37,7 @@ namespace {
 
 using namespace dev;
 
-template <int K, int F, bool EXPORT, typename T>
+template <int K, int F, bool EXPORT, typename T, bool FILL>
 #ifndef BFM_PERIODIC_OCC
 // Three waves per SIMD: the LDS ring of a 50-row window allows twelve per CU.
 #define BFM_PERIODIC_OCC __attribute__((amdgpu_waves_per_eu(3)))
@@ -62,7 +64,12 @@ void periodic_kernel(PeriodicArgs a)
     float* const myring = ring + tid;
 
     // ---- history (Eq. 5-6) ----
-    const double c = (double)load_obs(Y, lane_bytes);
+    // c centres the series (its first observation, or with FILL its first
+    // finite one, which also fills a leading gap).
+    const float c0 = FILL ? first_finite(Y, ld, lane, N) : load_obs(Y, lane_bytes);
+    const double c = (double)c0;
+    Filler fill{c0};
+    auto obs = [&](float v) { return FILL ? fill(v) : v; };
     double A[F];
 #pragma unroll
     for (int u = 0; u < F; ++u) A[u] = 0.0;
@@ -86,11 +93,13 @@ void periodic_kernel(PeriodicArgs a)
     // Rows from a block boundary at or before n - H also go to the ring, so that
     // it holds the last H history rows when the history ends.
     const int B = ((n - H) / F) * F;
-    stream_aligned<F>(BlockCursorT<T>(Y, ld, lane), 0, B, hist, hist_pre);
+    stream_aligned<F>(BlockCursorT<T>(Y, ld, lane), 0, B,
+                      [&](int u, int t, float v) { hist(u, t, obs(v)); }, hist_pre);
     int slot = B % H;  // ring slot of the next row: t mod H
     stream_aligned<F>(
         BlockCursorT<T>(Y + (int64_t)B * ld, ld, lane), B, n,
         [&](int u, int t, float v) {
+            v = obs(v);
             hist(u, t, v);
             myring[slot * kPlainBlock] = v;
             slot = slot + 1 == H ? 0 : slot + 1;
@@ -202,6 +211,7 @@ void periodic_kernel(PeriodicArgs a)
         wslot = s0;
     };
     auto row = [&](int u, int t, float v, double thr) {
+        v = obs(v);
         myring[wslot * kPlainBlock] = v;
         wslot = wslot + 1 == H ? 0 : wslot + 1;
         Sp += ((double)v - (double)vo[u]) - gamma;
@@ -224,7 +234,9 @@ void periodic_kernel(PeriodicArgs a)
                       [&](int u, int t, float v) { row(u, t, v, bnd[t - n] * scale); }, pre_w);
 
     const bool bad = hist_bad || !isfinite(Sp);
-    const uint8_t st = bad ? BFM_ST_NONFINITE : degenerate ? BFM_ST_DEGENERATE_SIGMA : BFM_ST_OK;
+    // With FILL only a series without any finite value stays non-finite.
+    const uint8_t st = bad ? (FILL ? BFM_ST_INSUFFICIENT : BFM_ST_NONFINITE)
+                           : degenerate ? BFM_ST_DEGENERATE_SIGMA : BFM_ST_OK;
     if (!active) return;
 
     double mag = qnan;
@@ -236,11 +248,14 @@ void periodic_kernel(PeriodicArgs a)
     if (bad && !hist_bad) write_fit(true);
     if (EXPORT) {
         if (a.resid) {
+            Filler rfill{c0};
             for (int t = 0; t < N; ++t) {
                 double r = qnan;
-                if (st != BFM_ST_NONFINITE) {
+                float v = to_float(Y[(int64_t)t * ld + pix]);
+                if (FILL) v = rfill(v);
+                if (!bad) {
                     const int ph = t % F;
-                    r = (double)to_float(Y[(int64_t)t * ld + pix]) - c - beta[0] -
+                    r = (double)v - c - beta[0] -
                         beta[1] * ((double)(t + 1) - tc) / (double)n;
                     for (int j = 0; j < NH; ++j) r = fma(-hh[ph * NH + j], beta[2 + j], r);
                 }
@@ -542,38 +557,38 @@ hipError_t launch_split_ns(const PeriodicArgs& a, int order, int F, hipStream_t 
     return hipErrorInvalidValue;
 }
 
-template <int K, int F, typename T>
+template <int K, int F, typename T, bool FILL>
 hipError_t launch_kf(const PeriodicArgs& a, hipStream_t stream)
 {
     const dim3 grid((unsigned)((a.P + kPlainBlock - 1) / kPlainBlock));
     const size_t lds = (size_t)a.H * kPlainBlock * sizeof(float);
     if (a.resid || a.mosum)
-        hipLaunchKernelGGL((periodic_kernel<K, F, true, T>), grid, dim3(kPlainBlock), lds, stream, a);
+        hipLaunchKernelGGL((periodic_kernel<K, F, true, T, FILL>), grid, dim3(kPlainBlock), lds, stream, a);
     else
-        hipLaunchKernelGGL((periodic_kernel<K, F, false, T>), grid, dim3(kPlainBlock), lds, stream, a);
+        hipLaunchKernelGGL((periodic_kernel<K, F, false, T, FILL>), grid, dim3(kPlainBlock), lds, stream, a);
     return hipGetLastError();
 }
 
-template <int F, typename T>
+template <int F, typename T, bool FILL>
 hipError_t launch_f(const PeriodicArgs& a, int order, hipStream_t stream)
 {
     switch (order) {
-    case 0: return launch_kf<0, F, T>(a, stream);
-    case 1: return launch_kf<1, F, T>(a, stream);
-    case 2: return launch_kf<2, F, T>(a, stream);
-    case 3: return launch_kf<3, F, T>(a, stream);
-    case 4: return launch_kf<4, F, T>(a, stream);
+    case 0: return launch_kf<0, F, T, FILL>(a, stream);
+    case 1: return launch_kf<1, F, T, FILL>(a, stream);
+    case 2: return launch_kf<2, F, T, FILL>(a, stream);
+    case 3: return launch_kf<3, F, T, FILL>(a, stream);
+    case 4: return launch_kf<4, F, T, FILL>(a, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <typename T>
+template <typename T, bool FILL = false>
 hipError_t launch_t(const PeriodicArgs& a, int order, int F, hipStream_t stream)
 {
     switch (F) {
-    case 12: return launch_f<12, T>(a, order, stream);
-    case 23: return launch_f<23, T>(a, order, stream);
-    case 24: return launch_f<24, T>(a, order, stream);
+    case 12: return launch_f<12, T, FILL>(a, order, stream);
+    case 23: return launch_f<23, T, FILL>(a, order, stream);
+    case 24: return launch_f<24, T, FILL>(a, order, stream);
     default: return hipErrorInvalidValue;
     }
 }

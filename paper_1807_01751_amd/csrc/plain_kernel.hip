@@ -18,7 +18,10 @@
 //       hi/lo = max/min num             MOSUM value of largest magnitude
 //
 // Neither the predictions nor the MOSUM process are materialised: Y is read
-// once and each pixel writes a break index and a magnitude.
+// once and each pixel writes a break index and a magnitude.  With FILL, missing
+// (non-finite) observations are filled forward (backward for a leading gap) as
+// the rows are consumed (footnote of Section 3), and the filled series is
+// monitored.
 #include <climits>
 #include <cmath>
 
@@ -35,7 +38,7 @@ using namespace dev;
 #endif
 constexpr int kU = BFM_PLAIN_ROWS;  // rows per prefetch chunk
 
-template <int NP, bool EXPORT>
+template <int NP, bool EXPORT, bool FILL>
 __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
 {
     extern __shared__ float ring[];  // H rows x kPlainBlock lanes
@@ -53,7 +56,12 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
     const ctab bnd = as_const(a.bnd);
     float* myring = ring + tid;
 
-    const double c = (double)load_obs(Y, lane_bytes);
+    // c centres the series (its first observation, or with FILL its first
+    // finite one, which also fills a leading gap).
+    const float c0 = FILL ? first_finite(Y, ld, lane, N) : load_obs(Y, lane_bytes);
+    const double c = (double)c0;
+    Filler fill{c0};
+    auto obs = [&](float v) { return FILL ? fill(v) : v; };
     double bq[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) bq[j] = 0.0;
@@ -63,6 +71,7 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
     // History rows before the last window: fit accumulation only.
     const int tail0 = n - H;
     stream_rows<kU>(ObsCursor{Y + (int64_t)(0) * ld, ld, lane_bytes}, 0, tail0, [&](int t, float v) {
+        v = obs(v);
         const double d = (double)v - c;
         yy = fma(d, d, yy);
         const ctab qt = q + t * NP;
@@ -73,6 +82,7 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
     // Last H history rows: also start the first window and fill the ring.
     int slot = tail0 % H;
     stream_rows<kU>(ObsCursor{Y + (int64_t)(tail0) * ld, ld, lane_bytes}, tail0, n, [&](int t, float v) {
+        v = obs(v);
         const double d = (double)v - c;
         yy = fma(d, d, yy);
         S += d;
@@ -145,6 +155,7 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
             }
         };
         auto row = [&](int u, int t, float v, bool flat) {
+            v = obs(v);
             int s = s0 + u;
             s -= s >= H ? H : 0;
             myring[s * kPlainBlock] = v;
@@ -157,6 +168,7 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
                         [&](int u, int t, float v) { row(u, t, v, false); }, pre);
     } else {
         auto row = [&](int t, float v, bool flat) {
+            v = obs(v);
             const float vo1 = myring[slot * kPlainBlock];
             myring[slot * kPlainBlock] = v;
             slot = (slot + 1 == H) ? 0 : slot + 1;
@@ -169,7 +181,9 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
     }
 
     const bool bad = hist_bad || !isfinite(S);
-    const uint8_t st = bad ? BFM_ST_NONFINITE : degenerate ? BFM_ST_DEGENERATE_SIGMA : BFM_ST_OK;
+    // With FILL only a series without any finite value stays non-finite.
+    const uint8_t st = bad ? (FILL ? BFM_ST_INSUFFICIENT : BFM_ST_NONFINITE)
+                           : degenerate ? BFM_ST_DEGENERATE_SIGMA : BFM_ST_OK;
     if (!active) return;
 
     double mag = qnan;
@@ -181,10 +195,13 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
     if (bad && !hist_bad) write_fit(true);
     if (EXPORT) {
         if (a.resid) {
+            Filler rfill{c0};
             for (int t = 0; t < N; ++t) {
                 double r = qnan;
-                if (st != BFM_ST_NONFINITE) {
-                    r = (double)Y[(int64_t)t * ld + pix] - c;
+                float v = Y[(int64_t)t * ld + pix];
+                if (FILL) v = rfill(v);
+                if (!bad) {
+                    r = (double)v - c;
                     const ctab qt = q + t * NP;
                     for (int j = 0; j < NP; ++j) r = fma(-qt[j], bq[j], r);
                 }
@@ -208,12 +225,19 @@ __global__ __launch_bounds__(256) void fill_status_kernel(const T* __restrict__ 
     const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (pix >= P) return;
     bool bad = false;
-    if (mask_mode != BFM_MASK_NAN)
+    uint8_t st = st0;
+    if (mask_mode == BFM_MASK_FILL) {
+        // Filling leaves a series non-finite only when it has no finite value.
+        bool any = false;
+        for (int t = 0; t < N && !any; ++t) any = isfinite(to_float(Y[(int64_t)t * ld + pix]));
+        if (!any) st = BFM_ST_INSUFFICIENT;
+    } else if (mask_mode != BFM_MASK_NAN) {
         for (int t = 0; t < N; ++t) {
             bool used = mask_mode == BFM_MASK_NONE || valid[(int64_t)t * ldv + pix] != 0;
             bad |= used && !isfinite(to_float(Y[(int64_t)t * ld + pix]));
         }
-    const uint8_t st = bad ? (uint8_t)BFM_ST_NONFINITE : st0;
+        if (bad) st = BFM_ST_NONFINITE;
+    }
     const double qnan = __builtin_nan("");
     const int f64 = out.out_dtype == BFM_OUT_F64;
     out.brk[pix] = -1;
@@ -228,17 +252,23 @@ __global__ __launch_bounds__(256) void fill_status_kernel(const T* __restrict__ 
         for (int m = 0; m < N - n; ++m) put_out(out.mosum, (int64_t)m * P + pix, qnan, f64);
 }
 
-template <int NP>
-hipError_t launch_np(const PlainArgs& a, hipStream_t stream)
+template <int NP, bool FILL>
+hipError_t launch_np_fill(const PlainArgs& a, hipStream_t stream)
 {
     const dim3 grid((unsigned)((a.P + kPlainBlock - 1) / kPlainBlock));
     const size_t lds = (size_t)a.H * kPlainBlock * sizeof(float);
     const bool exp = a.resid || a.mosum;
     if (exp)
-        hipLaunchKernelGGL((plain_kernel<NP, true>), grid, dim3(kPlainBlock), lds, stream, a);
+        hipLaunchKernelGGL((plain_kernel<NP, true, FILL>), grid, dim3(kPlainBlock), lds, stream, a);
     else
-        hipLaunchKernelGGL((plain_kernel<NP, false>), grid, dim3(kPlainBlock), lds, stream, a);
+        hipLaunchKernelGGL((plain_kernel<NP, false, FILL>), grid, dim3(kPlainBlock), lds, stream, a);
     return hipGetLastError();
+}
+
+template <int NP>
+hipError_t launch_np(const PlainArgs& a, hipStream_t stream)
+{
+    return a.fill ? launch_np_fill<NP, true>(a, stream) : launch_np_fill<NP, false>(a, stream);
 }
 
 }  // namespace

@@ -11,6 +11,11 @@ Recipe (per pixel i, time t = 1..N; every draw seeded):
   a_ij ~ U(0, 0.2), phi_ij ~ U(0, 2 pi), eps_it ~ N(0, 0.02^2)
   with probability ``step_frac`` the pixel gets y_t += step for t >= tau_i,
   tau_i ~ U{n+1..N} (a break inside the monitoring period).
+Unevenly sampled scenes (Section 4's Landsat stack, f = 365 on day numbers):
+``acquisition_days`` draws day numbers with gaps of 8-48 days, and
+``make_series(..., times=days, freq=365, trend=2e-5)`` evaluates the same
+recipe at those times (t replaced by the day number; the planted shift still
+starts at an observation index).
 Missing observations: a share ``iid`` of independent Bernoulli gaps plus cloud
 runs of length U{3..15} whose starts are a Bernoulli process tuned so the runs
 cover a share ``runs`` of the series.  Paper context: Section 4 builds its
@@ -30,13 +35,25 @@ def _gen(device, seed):
     return g
 
 
+def acquisition_days(N: int, *, seed: int = 0, start: float = 18.0):
+    """Day numbers (float64 numpy array, strictly increasing) of N acquisitions:
+    gaps of 8 or 16 days (two sensors' revisits) and 32 or 48 days (scenes lost
+    to clouds), starting at day ``start``."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    gaps = rng.choice(np.array([8.0, 16.0, 16.0, 16.0, 32.0, 48.0]), N - 1)
+    return start + np.concatenate([[0.0], np.cumsum(gaps)])
+
+
 def make_series(P: int, N: int, n: int, order: int = 3, *, freq: float = 23.0, seed: int = 0,
                 step_frac: float = 0.2, step: float = -0.3, noise: float = 0.02,
-                device="cpu", chunk_rows: int = 64):
+                times=None, trend: float = 5e-4, device="cpu", chunk_rows: int = 64):
     """Return (Y, truth): Y is a time-major float32 tensor of shape (N, P).
 
     ``truth`` holds the per-pixel draws: ``has_step`` (bool), ``tau`` (int64, the
-    1-based time of the planted shift; meaningful where has_step).
+    1-based observation index of the planted shift; meaningful where has_step).
+    ``times`` (N values) replaces t = 1..N in the signal; ``trend`` is the slope
+    per unit of t.
     """
     device = torch.device(device)
     g = _gen(device, seed)
@@ -48,9 +65,11 @@ def make_series(P: int, N: int, n: int, order: int = 3, *, freq: float = 23.0, s
     for t0 in range(0, N, chunk_rows):
         t1 = min(N, t0 + chunk_rows)
         t = torch.arange(t0 + 1, t1 + 1, device=device, dtype=torch.float64)[:, None]
-        y = 0.5 + 5e-4 * t + torch.zeros(t1 - t0, P, device=device, dtype=torch.float64)
+        tv = t if times is None else torch.as_tensor(times[t0:t1], dtype=torch.float64,
+                                                     device=device)[:, None]
+        y = 0.5 + trend * tv + torch.zeros(t1 - t0, P, device=device, dtype=torch.float64)
         for j in range(order):
-            y += amp[j] * torch.sin(2 * math.pi * (j + 1) * t / freq + phase[j])
+            y += amp[j] * torch.sin(2 * math.pi * (j + 1) * tv / freq + phase[j])
         y += noise * torch.randn(t1 - t0, P, generator=g, device=device, dtype=torch.float64)
         y += step * (has_step & (t >= tau)).to(torch.float64)
         Y[t0:t1] = y.to(torch.float32)

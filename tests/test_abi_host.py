@@ -43,7 +43,7 @@ def test_params_struct_matches_header(bfm):
     # field order and types of bfm_params / bfm_outputs as declared in the header
     src = open(HEADER).read()
     body = re.search(r"typedef struct \{([^{}]*)\} bfm_params;", src, re.S).group(1)
-    fields = re.findall(r"(int32_t|double)\s+(\w+);", body)
+    fields = re.findall(r"(int32_t|double)\s+\*?(\w+);", body)
     names = [f[0] for f in bfm.Params._fields_]
     assert [f[1] for f in fields] == [n.rstrip("_") for n in names]
     body = re.search(r"typedef struct \{([^{}]*)\} bfm_outputs;", src, re.S).group(1)
@@ -56,7 +56,11 @@ def test_params_struct_matches_header(bfm):
     (dict(N=100, n=50, freq=float("inf")), -1), (dict(N=100, n=50, lam=0.0), -1),
     (dict(N=100, n=50, h=0.0), -1), (dict(N=100, n=50, h=1.01), -1),
     (dict(N=100, n=50, h_window=51), -1), (dict(N=100, n=50, h_window=-1), -1),
-    (dict(N=100, n=50, mask_mode=3), -1),
+    (dict(N=100, n=50, mask_mode=4), -1),
+    (dict(N=5, n=3, times=[1.0, 2.0, 2.0, 3.0, 4.0]), -1),
+    (dict(N=5, n=3, times=[1.0, 2.0, 3.0, 2.5, 4.0]), -1),
+    (dict(N=5, n=3, times=[1.0, 2.0, float("nan"), 3.0, 4.0]), -1),
+    (dict(N=5, n=3, times=[1.0, 2.0, 3.0, 4.0, float("inf")]), -1),
 ])
 def test_check_params_rejects(bfm, kw, code):
     prm = bfm.make_params(**kw)
@@ -71,6 +75,8 @@ def test_check_params_layout_and_accepts(bfm):
     bfm.check_params(prm, 0, 0)
     bfm.check_params(bfm.make_params(400, 200, 3, h=1.0), 5, 8)
     bfm.check_params(bfm.make_params(400, 200, 3, h_window=200), 5, 8)
+    bfm.check_params(bfm.make_params(5, 3, 0, times=[0.5, 2.0, 9.0, 9.5, 30.0]), 5, 8)
+    bfm.check_params(bfm.make_params(400, 200, 3, mask_mode=bfm.MASK_FILL), 5, 8)
     with pytest.raises(bfm.BfmError) as e:
         bfm.check_params(prm, 10, 9)
     assert e.value.code == bfm.E_LAYOUT
@@ -121,6 +127,29 @@ def test_host_operators_span_and_windows(bfm, N, n, order, freq, h, hw):
     t1 = np.arange(n + 1, N + 1) / n
     ref = 2.5 * np.sqrt(np.where(t1 <= np.e, 1.0, np.log(np.maximum(t1, 1.0))))
     np.testing.assert_allclose(bnd, ref, rtol=1e-15)
+
+
+def test_host_operators_in_observation_time(bfm):
+    """Operators built from observation times (day numbers, f = 365): the
+    history rows stay orthonormal, an exact season-trend series in those times
+    is reproduced everywhere and bmap returns its coefficients."""
+    N, n, order, H = 288, 144, 3, 72
+    rng = np.random.default_rng(3)
+    days = 18.0 + np.concatenate([[0.0], np.cumsum(rng.choice([8.0, 16.0, 32.0, 48.0], N - 1))])
+    q, w, bnd, bmap = (x.numpy() for x in bfm.host_operators(
+        bfm.make_params(N, n, order, 365.0, 0.25, H, 2.5, times=days)))
+    p = 2 + 2 * order
+    np.testing.assert_allclose(q[:n].T @ q[:n], np.eye(p), atol=1e-13)
+    cols = [np.ones(N), days]
+    for j in range(1, order + 1):
+        cols += [np.sin(2 * np.pi * j * days / 365.0), np.cos(2 * np.pi * j * days / 365.0)]
+    X = np.stack(cols, axis=1)
+    beta0 = np.array([0.4, 3e-5, 0.1, -0.05, 0.03, 0.02, -0.01, 0.015])
+    y = X @ beta0
+    bq = q[:n].T @ y[:n]
+    np.testing.assert_allclose(q @ bq, y, atol=1e-11)
+    np.testing.assert_allclose(bmap @ bq, beta0, rtol=1e-8, atol=1e-13)
+    np.testing.assert_allclose(w[5], q[n + 5 - H + 1:n + 6].sum(axis=0), atol=1e-12)
 
 
 def test_host_operators_rank_deficient(bfm):
