@@ -233,6 +233,38 @@ int bfm_autotune(bfm_ctx *ctx, const bfm_params *prm, const void *Y, int32_t y_d
 int bfm_tune_set(bfm_ctx *ctx, const bfm_params *prm, int32_t y_dtype, int64_t P, int32_t split);
 
 /*
+ * Critical value lambda of Eq. 4 by simulation.  Section 2.1 chooses lambda so
+ * that, when nothing changes, the MOSUM crosses lambda sqrt(log+(t/n)) with
+ * probability alpha, and finds it by simulation for given alpha, window h and
+ * horizon N/n.  These entry points simulate the MOSUM of Eq. 3 under no change
+ * at the resolution of the series (n_hist, n_obs and the window H of prm; its
+ * other fields are validated but unused): with i.i.d. standard normal errors
+ * z_1..z_N and the intercept model (whose residual MOSUM has the same limiting
+ * process as the season-trend model's, W(t) - W(t-h) - h W(1)),
+ *   M_k = (sum_{i=k-H+1..k} z_i - (H/n) sum_{i=1..n} z_i) / sqrt(n),
+ *   S   = max_{k=n+1..N} |M_k| / sqrt(log+(k/n)),
+ * and a path crosses lambda sqrt(log+) iff S > lambda.  The normals of path q
+ * come from Philox4x64-10 (Salmon et al., SC 2011) with key (seed, 0) and
+ * counter (j, q, 0, 0) for steps 4j+1..4j+4, through the Box-Muller transform
+ * of the uniforms ((w >> 11) + 1/2) 2^-53: results depend only on (seed, q),
+ * not on how paths are split over calls.
+ *
+ * bfm_mosum_null_sup writes S of paths path0 .. path0+paths-1 to sup (device,
+ * double[paths]); it allocates nothing.
+ * bfm_critical_value returns in *lambda (host) the ceil((1 - alpha) paths)-th
+ * smallest S over paths 0 .. paths-1 (so at most a share alpha of the paths
+ * cross it), selected on the device.  It allocates paths * 8 + 1024 bytes of
+ * device memory for the call and synchronises `stream` before returning.
+ * Errors: BFM_E_INVAL (NULL ctx/prm/output, bad parameters, window outside
+ * [1, n_hist], alpha outside (0, 1), paths < 1 or > 2^31), BFM_E_NOMEM,
+ * BFM_E_HIP.
+ */
+int bfm_mosum_null_sup(bfm_ctx *ctx, const bfm_params *prm, uint64_t seed, int64_t path0,
+                       int64_t paths, double *sup, void *stream);
+int bfm_critical_value(bfm_ctx *ctx, const bfm_params *prm, double alpha, int64_t paths,
+                       uint64_t seed, double *lambda, void *stream);
+
+/*
  * Serving.  A server runs requests of different sizes and parameters as they
  * arrive, several at a time: each admitted request runs on one of `slots` HIP
  * streams of the server's device (non-blocking, default priority), so the work

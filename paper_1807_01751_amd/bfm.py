@@ -35,7 +35,8 @@ _ERRNAMES = {E_INVAL: "BFM_E_INVAL", E_LAYOUT: "BFM_E_LAYOUT", E_NOMEM: "BFM_E_N
 EXPORTS = ("bfm_version", "bfm_last_error", "bfm_check_params", "bfm_create", "bfm_destroy",
            "bfm_fit_monitor", "bfm_fit_monitor_typed", "bfm_host_operators", "bfm_request_bytes",
            "bfm_server_create", "bfm_server_submit", "bfm_server_wait", "bfm_server_release",
-           "bfm_server_take", "bfm_autotune", "bfm_tune_set",
+           "bfm_server_take", "bfm_autotune", "bfm_tune_set", "bfm_mosum_null_sup",
+           "bfm_critical_value",
            "bfm_server_get_stats", "bfm_server_destroy")
 WANT = {"mag": 1, "sigma": 2, "status": 4, "beta": 8, "resid": 16, "mosum": 32}
 
@@ -131,6 +132,9 @@ def load():
     lib.bfm_autotune.argtypes = [vp, P_, vp, ctypes.c_int32, i64, i64, vp, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_double)]
     lib.bfm_tune_set.argtypes = [vp, P_, ctypes.c_int32, i64, ctypes.c_int32]
+    lib.bfm_mosum_null_sup.argtypes = [vp, P_, ctypes.c_uint64, i64, i64, vp, vp]
+    lib.bfm_critical_value.argtypes = [vp, P_, ctypes.c_double, i64, ctypes.c_uint64,
+                                       ctypes.POINTER(ctypes.c_double), vp]
     R_ = ctypes.POINTER(Request)
     lib.bfm_request_bytes.argtypes = [R_, ctypes.POINTER(ctypes.c_size_t)]
     lib.bfm_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_size_t]
@@ -272,6 +276,32 @@ def fit_monitor(Y: torch.Tensor, *, n: int, order: int = 3, freq: float = 23.0, 
                                       vptr, ldv, ctypes.byref(o), s.cuda_stream)
     _raise(rc)
     return res
+
+
+def mosum_null_sup(*, n: int, N: int, h: float = 0.25, h_window: int = 0, seed: int = 0,
+                   path0: int = 0, paths: int = 100000, device: int = 0,
+                   stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+    """bfm_mosum_null_sup: the sup statistic of simulated no-change MOSUM paths
+    path0 .. path0+paths-1 (float64 tensor on the device)."""
+    prm = make_params(N, n, 0, 23.0, h, h_window, 1.0, MASK_NONE)
+    sup = torch.empty(int(paths), dtype=torch.float64, device=f"cuda:{device}")
+    s = stream if stream is not None else torch.cuda.current_stream(sup.device)
+    _raise(load().bfm_mosum_null_sup(context(device), ctypes.byref(prm), ctypes.c_uint64(seed),
+                                     int(path0), int(paths), sup.data_ptr(), s.cuda_stream))
+    return sup
+
+
+def critical_value(alpha: float, *, n: int, N: int, h: float = 0.25, h_window: int = 0,
+                   paths: int = 100000, seed: int = 0, device: int = 0,
+                   stream: torch.cuda.Stream | None = None) -> float:
+    """bfm_critical_value: lambda of Eq. 4 for (alpha, window, N/n) by simulation."""
+    prm = make_params(N, n, 0, 23.0, h, h_window, 1.0, MASK_NONE)
+    out = ctypes.c_double()
+    s = stream if stream is not None else torch.cuda.current_stream(torch.device(f"cuda:{device}"))
+    _raise(load().bfm_critical_value(context(device), ctypes.byref(prm), ctypes.c_double(alpha),
+                                     int(paths), ctypes.c_uint64(seed), ctypes.byref(out),
+                                     s.cuda_stream))
+    return out.value
 
 
 def autotune(Y: torch.Tensor, *, n: int, order: int = 3, freq: float = 23.0, h: float = 0.25,

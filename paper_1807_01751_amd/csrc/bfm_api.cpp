@@ -512,6 +512,64 @@ int split_shape(bfm_ctx* ctx, const bfm_params* prm, int32_t y_dtype, int64_t P,
 
 }  // namespace
 
+namespace {
+
+// Window and sizes of the simulated null MOSUM for these parameters.
+int null_shape(bfm_ctx* ctx, const bfm_params* prm, int* H)
+{
+    if (!ctx) return fail(BFM_E_INVAL, "ctx is NULL");
+    int rc = check(prm, 0, 0);
+    if (rc) return rc;
+    *H = bfm::window_length(*prm, prm->n_hist);
+    if (*H < 1 || *H > prm->n_hist)
+        return fail(BFM_E_INVAL, "window length %d must be in [1, n_hist]", *H);
+    return BFM_SUCCESS;
+}
+
+}  // namespace
+
+int bfm_mosum_null_sup(bfm_ctx* ctx, const bfm_params* prm, uint64_t seed, int64_t path0, int64_t paths,
+                       double* sup, void* stream)
+{
+    int H = 0;
+    int rc = null_shape(ctx, prm, &H);
+    if (rc) return rc;
+    if (paths < 0 || path0 < 0) return fail(BFM_E_INVAL, "path0 and paths must be >= 0");
+    if (paths == 0) return BFM_SUCCESS;
+    if (!sup) return fail(BFM_E_INVAL, "sup is NULL");
+    DeviceGuard g(ctx->device);
+    hipError_t e = bfm::launch_mosum_null_sup(prm->n_hist, prm->n_obs, H, seed, path0, paths, sup,
+                                              static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? BFM_SUCCESS : hip_fail(e, "null MOSUM kernel launch");
+}
+
+int bfm_critical_value(bfm_ctx* ctx, const bfm_params* prm, double alpha, int64_t paths, uint64_t seed,
+                       double* lambda, void* stream)
+{
+    int H = 0;
+    int rc = null_shape(ctx, prm, &H);
+    if (rc) return rc;
+    if (!(alpha > 0 && alpha < 1)) return fail(BFM_E_INVAL, "alpha must be in (0, 1)");
+    if (paths < 1 || paths > ((int64_t)1 << 31)) return fail(BFM_E_INVAL, "paths must be in [1, 2^31]");
+    if (!lambda) return fail(BFM_E_INVAL, "lambda is NULL");
+    int64_t rank = (int64_t)std::ceil((1.0 - alpha) * (double)paths - 1e-9);
+    rank = std::max<int64_t>(1, std::min(rank, paths));
+    DeviceGuard g(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* buf = nullptr;
+    hipError_t e = hipMalloc(&buf, (size_t)paths * sizeof(double) + 256 * sizeof(uint32_t));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(null paths)");
+    double* sup = static_cast<double*>(buf);
+    uint32_t* counts = reinterpret_cast<uint32_t*>(sup + paths);
+    e = bfm::launch_mosum_null_sup(prm->n_hist, prm->n_obs, H, seed, 0, paths, sup, s);
+    if (e == hipSuccess) e = bfm::select_rank(sup, paths, rank, counts, lambda, s);
+    // select_rank has synchronised the stream; the buffer is idle.
+    hipError_t ef = hipFree(buf);
+    if (e != hipSuccess) return hip_fail(e, "critical value");
+    if (ef != hipSuccess) return hip_fail(ef, "hipFree(null paths)");
+    return BFM_SUCCESS;
+}
+
 int bfm_tune_set(bfm_ctx* ctx, const bfm_params* prm, int32_t y_dtype, int64_t P, int32_t split)
 {
     int H = 0, F = 0;

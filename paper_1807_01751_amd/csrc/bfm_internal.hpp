@@ -109,6 +109,7 @@ struct PlainArgs {
 };
 
 hipError_t launch_plain(const PlainArgs& a, int p, hipStream_t stream);
+hipError_t launch_plain_fill(const PlainArgs& a, int p, hipStream_t stream);
 
 // Arguments of the period-blocked plain kernel.
 struct PeriodicArgs {
@@ -173,6 +174,14 @@ hipError_t launch_masked_periodic_bf16(const MaskedArgs& a, int order, int mask_
 hipError_t launch_masked_periodic_f16(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
 size_t masked_periodic_lds_bytes(int cap);
 size_t masked_lds_bytes(int cap);
+
+// Null-path MOSUM sup statistics for the simulated critical value (one lane per
+// path; sup[i] for path path0 + i) and the device rank selection over them
+// (rank 1-based among cnt positive doubles; counts: 256 uint32 of scratch).
+hipError_t launch_mosum_null_sup(int n, int N, int H, uint64_t seed, int64_t path0, int64_t paths,
+                                 double* sup, hipStream_t stream);
+hipError_t select_rank(const double* v, int64_t cnt, int64_t rank, uint32_t* counts, double* out,
+                       hipStream_t stream);
 
 // Every pixel gets `st` (or NONFINITE if one of its used observations is not
 // finite), brk = -1 and NaN floating outputs: used when the parameters make
