@@ -15,7 +15,12 @@ mixed-precision leg ("mixed") stores the tile in FP16 (half the bytes) with the
 same FP64 arithmetic, and reports how its break indices and magnitudes compare
 with the float32 leg.  A serving leg ("serving") runs a stream of requests of
 mixed sizes and parameters through the serving runtime under Poisson arrivals
-and reports latency percentiles beside throughput.
+and reports latency percentiles beside throughput.  Three method variants
+follow under "variants": the tile with 10% missing observations filled forward
+(fill), a scene of the Chile experiment's shape (2400 x 1851 pixels, 288
+unevenly spaced acquisitions, day numbers with f = 365, n = 144, h = 72) on
+the table-driven kernel (times), and the simulated critical value from one
+million no-change paths (lambda).
 
 Prints one JSON line.  Run with --gpus 1 (the default); more GPUs are not
 supported by this benchmark.
@@ -40,11 +45,11 @@ MISSING = 0.25
 # period, so the period-blocked kernels are used), the rocprofv3 summaries kept
 # for each, and the workload each is timed on.
 LEGS = {
-    "plain": {"kernel": "::periodic_kernel<3, 23, false, float>(",
+    "plain": {"kernel": "::periodic_kernel<3, 23, false, float, false>(",
               "traffic": os.path.join(PROFILES, "traffic_plain_1024x1024_N400.json"),
               "trace_md": os.path.join(PROFILES, "plain_periodic_k3_f23_1024x1024_N400_kernel_trace.md"),
               "workload": "1024x1024 pixels, N=400"},
-    "mixed": {"kernel": "::periodic_kernel<3, 23, false, bfm::dev::f16_t>(",
+    "mixed": {"kernel": "::periodic_kernel<3, 23, false, bfm::dev::f16_t, false>(",
               "traffic": os.path.join(PROFILES, "traffic_mixed_f16_1024x1024_N400.json"),
               "trace_md": os.path.join(PROFILES, "mixed_periodic_f16_k3_f23_1024x1024_N400_kernel_trace.md"),
               "workload": "1024x1024 pixels, N=400, FP16-stored", "y_bytes": 2},
@@ -53,7 +58,19 @@ LEGS = {
                "trace_md": os.path.join(PROFILES,
                                         "masked_periodic_k3_f23_1024x1024_N400_nan25_kernel_trace.md"),
                "workload": "1024x1024 pixels, N=400, 25% NaN"},
+    "fill": {"kernel": "::periodic_kernel<3, 23, false, float, true>(",
+             "traffic": os.path.join(PROFILES, "traffic_fill_1024x1024_N400_miss10.json"),
+             "trace_md": os.path.join(PROFILES, "fill_periodic_k3_f23_1024x1024_N400_miss10_kernel_trace.md"),
+             "workload": "1024x1024 pixels, N=400, 10% missing, filled"},
+    "times": {"kernel": "::plain_kernel<8, false, false>(",
+              "traffic": os.path.join(PROFILES, "traffic_times_2400x1851_N288.json"),
+              "trace_md": os.path.join(PROFILES, "times_plain_k3_f365_2400x1851_N288_kernel_trace.md"),
+              "workload": "2400x1851 pixels, N=288 acquisition days, f=365",
+              "pixels": 2400 * 1851, "n_obs": 288},
 }
+CHILE_P, CHILE_N, CHILE_n, CHILE_H = 2400 * 1851, 288, 144, 72
+FILL_MISSING = 0.10
+LAMBDA_PATHS = 1 << 20
 PROFILE_CMD = ("rocprofv3 {flags} -f csv -d <dir> -o run -- python3 bench.py --steps 10 "
                "--warmup 2 --no-cpu-baseline --copy-calibration")
 
@@ -125,20 +142,28 @@ def summarize_profiles(d):
         with open(os.path.join(d, sub + ".log")) as f:
             shas |= set(re.findall(r"kernel_sha=([0-9a-f]+)", f.read()))
     assert shas == {kernel_sha()}, f"profiles were taken on other sources: {shas}"
-    trace = _csv(glob.glob(os.path.join(d, "trace", "*kernel_stats.csv"))[0])
+    trace = _csv(glob.glob(os.path.join(d, "trace", "*kernel_trace.csv"))[0])
     counters = {sub: _csv(glob.glob(os.path.join(d, sub, "*counter_collection.csv"))[0])
                 for sub in ("fetch", "write")}
     os.makedirs(PROFILES, exist_ok=True)
     for leg, spec in LEGS.items():
         KERNEL = spec["kernel"]
-        P_ALG = (spec.get("y_bytes", 4) * N + 8) * P
-        stats = [r for r in trace if KERNEL in r["Name"]]
-        assert stats, f"{leg} kernel missing from the trace"
-        st = stats[0]
+        pixels = spec.get("pixels", P)
+        P_ALG = (spec.get("y_bytes", 4) * spec.get("n_obs", N) + 8) * pixels
+        # The leg's own launches: its kernel over the whole tile (one lane per
+        # pixel, 64-lane workgroups); the serving leg runs the same kernels on
+        # smaller requests.
+        grid = (pixels + 63) // 64 * 64
+        disp = [r for r in trace if KERNEL in r["Kernel_Name"] and int(r["Grid_Size_X"]) == grid]
+        assert disp, f"{leg} kernel missing from the trace"
+        dur = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in disp]
+        st = {"Name": disp[0]["Kernel_Name"], "Calls": len(dur), "MinNs": min(dur), "MaxNs": max(dur),
+              "AverageNs": sum(dur) / len(dur)}
         per = {}
         for counter, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
             rows = counters[sub]
-            k = [float(r["Counter_Value"]) for r in rows if KERNEL in r["Kernel_Name"]]
+            k = [float(r["Counter_Value"]) for r in rows
+                 if KERNEL in r["Kernel_Name"] and int(r["Grid_Size"]) == grid]
             copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
             calib = float(copies[-1]["Counter_Value"])  # the 1 GiB copy runs last
             factor = (1 << 30) / (calib * 1024.0)       # bytes per counted byte
@@ -158,10 +183,12 @@ def summarize_profiles(d):
             f.write(f"# rocprofv3 kernel trace: {KERNEL.strip(':(')}, {spec['workload']}\n\n")
             f.write("Command (from the repository root, on one MI355X):\n\n    "
                     + PROFILE_CMD.format(flags="--kernel-trace --stats") + "\n\n")
+            f.write(f"Launches over the whole workload (grid of {grid} work-items) only.\n\n")
             f.write("| kernel | calls | average ns | min ns | max ns |\n|---|---|---|---|---|\n")
             f.write(f"| {st['Name']} | {st['Calls']} | {avg_ns:.0f} | {st['MinNs']} | "
                     f"{st['MaxNs']} |\n\n")
-            f.write(f"Algorithmic bytes per launch: {P_ALG} ({spec.get('y_bytes', 4)}N + 8 per pixel). "
+            f.write(f"Algorithmic bytes per launch: {P_ALG} ({spec.get('y_bytes', 4)}N + 8 per pixel, "
+                    f"N = {spec.get('n_obs', N)}, {spec.get('pixels', P)} pixels). "
                     f"At the average "
                     f"duration this is {P_ALG / avg_ns:.1f} GB/s "
                     f"({P_ALG / avg_ns / HBM_PEAK_GBS:.3f} of 8 TB/s).\n\n")
@@ -276,8 +303,9 @@ def serving_leg(bfm, dev, requests=400, payloads=24, slots=4, load=0.8, seed=5):
 
 
 def roofline(leg, mean_ms, y_bytes=4):
-    bytes_per_px = y_bytes * N + 4 + 4  # read y once; write int32 brk + FP32 mag
-    alg_bytes = bytes_per_px * P
+    spec = LEGS[leg]
+    bytes_per_px = y_bytes * spec.get("n_obs", N) + 4 + 4  # read y once; write int32 brk + FP32 mag
+    alg_bytes = bytes_per_px * spec.get("pixels", P)
     achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_per_launch(leg),
@@ -364,6 +392,48 @@ def main():
     log(f"bench: masked {tm['ms_per_step']:.4f} ms/step wall, kernel mean {tm['mean']:.4f} ms")
     del Ym
 
+    # Fill leg: 10% missing (half iid, half cloud runs), filled forward as read.
+    r = split_rate(FILL_MISSING)
+    Yf = apply_missing(Y.clone(), make_missing(N, P, iid=r, runs=r, seed=8, device=dev))
+
+    def fstep():
+        bfm.fit_monitor(Yf, n=n, order=ORDER, freq=FREQ, h=H_FRAC, lam=LAM, mask_mode=bfm.MASK_FILL,
+                        outputs=("brk", "mag"), out_dtype=torch.float32, out=out)
+
+    log(f"bench: fill leg, warmup {args.warmup}, timing {args.steps} steps")
+    tf = timed(fstep, args.steps, args.warmup, stream)
+    log(f"bench: fill {tf['ms_per_step']:.4f} ms/step wall, kernel mean {tf['mean']:.4f} ms")
+    del Yf
+
+    # Irregular-time leg: a scene of the Chile experiment's shape at synthetic
+    # acquisition days (f = 365), table-driven plain kernel.
+    from paper_1807_01751_amd.synth import acquisition_days
+    days = acquisition_days(CHILE_N, seed=3)
+    Yc, _ = make_series(CHILE_P, CHILE_N, CHILE_n, ORDER, freq=365.0, times=days, trend=2e-5, seed=4,
+                        device=dev)
+    outc = {"brk": torch.empty(CHILE_P, dtype=torch.int32, device=dev),
+            "mag": torch.empty(CHILE_P, dtype=torch.float32, device=dev)}
+
+    def cstep():
+        bfm.fit_monitor(Yc, n=CHILE_n, order=ORDER, freq=365.0, h_window=CHILE_H, lam=LAM, times=days,
+                        outputs=("brk", "mag"), out_dtype=torch.float32, out=outc)
+
+    log(f"bench: times leg ({CHILE_P} pixels x {CHILE_N} days), timing {max(5, args.steps // 5)} steps")
+    tc = timed(cstep, max(5, args.steps // 5), min(args.warmup, 2), stream)
+    log(f"bench: times {tc['ms_per_step']:.4f} ms/step wall, kernel mean {tc['mean']:.4f} ms")
+    del Yc, outc
+
+    # Critical value by simulation: one million no-change paths at n = 200, N = 400, H = 50.
+    def lstep():
+        bfm.mosum_null_sup(n=n, N=N, h=H_FRAC, seed=1, paths=LAMBDA_PATHS)
+
+    tl = timed(lstep, 5, 1, stream)
+    t0 = time.perf_counter()
+    lam_crit = bfm.critical_value(0.05, n=n, N=N, h=H_FRAC, paths=LAMBDA_PATHS, seed=1)
+    lam_ms = (time.perf_counter() - t0) * 1e3
+    log(f"bench: lambda {lam_crit:.5f} from {LAMBDA_PATHS} paths: sup kernel {tl['mean']:.3f} ms, "
+        f"call {lam_ms:.2f} ms")
+
     log("bench: serving leg (Poisson arrivals, continuous batching)")
     serving = serving_leg(bfm, dev)
     log(f"bench: serving {serving['mpixel_s']} Mpixel/s, p50 {serving['p50_ms']} ms, "
@@ -422,6 +492,27 @@ def main():
                                             "(11 significant bits), FP64 arithmetic"},
                      "vs_f32_leg": {"brk_agreement": round(agree, 6), "max_abs_d_abs_mag": round(dmag, 5)},
                      "roofline": roofline("mixed", th["mean"], y_bytes=2)},
+           "variants": {
+               "fill": {"value": round(P / (tf["ms_per_step"] * 1e-3) / 1e6, 2), "unit": "Mpixel/s",
+                        "ms_per_step": round(tf["ms_per_step"], 5), "dtype": "f64",
+                        "config": {"workload": "the same tile with 10% missing (half iid, half "
+                                               "cloud runs), filled forward (backward for a "
+                                               "leading gap) as the rows are read"},
+                        "roofline": roofline("fill", tf["mean"])},
+               "times": {"value": round(CHILE_P / (tc["ms_per_step"] * 1e-3) / 1e6, 2),
+                         "unit": "Mpixel/s", "ms_per_step": round(tc["ms_per_step"], 5),
+                         "dtype": "f64",
+                         "config": {"workload": "a scene of the Chile experiment's shape: 2400x1851 "
+                                                "pixels, 288 acquisitions at synthetic day numbers "
+                                                "(gaps of 8-48 days), f=365, n=144, h=72, k=3",
+                                    "pixels": CHILE_P, "n_obs": CHILE_N},
+                         "roofline": roofline("times", tc["mean"])},
+               "lambda": {"value": round(LAMBDA_PATHS / (tl["mean"] * 1e-3) / 1e6, 2),
+                          "unit": "Mpaths/s", "sup_kernel_ms": round(tl["mean"], 4),
+                          "critical_value_call_ms": round(lam_ms, 3), "lambda": round(lam_crit, 6),
+                          "config": {"workload": "critical value for alpha=0.05, h=0.25, N/n=2 "
+                                                 "(n=200, N=400) from 1048576 simulated "
+                                                 "no-change MOSUM paths"}}},
            "serving": serving,
            "h2d": {"bytes": 4 * N * P, "ms": round(h2d_ms, 3),
                    "gb_per_s": round(4 * N * P / (h2d_ms * 1e-3) / 1e9, 1),
