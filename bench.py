@@ -7,6 +7,10 @@ lambda = 2.5, f = 23, seeded synthetic season-trend series with 20% planted
 steps (see paper_1807_01751_amd/synth.py).  Y is device-resident before the
 timed region; one step is one bfm_fit_monitor call over the whole tile
 (fit, sigma, MOSUM, boundary test, break index and magnitude), FP64 arithmetic.
+Before the W warmup steps the step runs untimed for at least a quarter of a
+second: the first tens of milliseconds of work after the GPU was idle run at
+lower clocks (measured: the same launch 2x slower in the first batch, steady
+after about 50 ms).
 
 After the headline leg, the same tile with 25% of its observations missing
 (NaN: half independent, half cloud runs of 3-15 rows) is timed through the
@@ -73,6 +77,7 @@ FILL_MISSING = 0.10
 LAMBDA_PATHS = 1 << 20
 PROFILE_CMD = ("rocprofv3 {flags} -f csv -d <dir> -o run -- python3 bench.py --steps 10 "
                "--warmup 2 --no-cpu-baseline --copy-calibration")
+PROFILED_LAUNCHES = 12  # --warmup 2 + --steps 10 of PROFILE_CMD
 
 
 def log(*a):
@@ -151,10 +156,13 @@ def summarize_profiles(d):
         pixels = spec.get("pixels", P)
         P_ALG = (spec.get("y_bytes", 4) * spec.get("n_obs", N) + 8) * pixels
         # The leg's own launches: its kernel over the whole tile (one lane per
-        # pixel, 64-lane workgroups); the serving leg runs the same kernels on
-        # smaller requests.
+        # pixel, 64-lane workgroups; the serving leg runs the same kernels on
+        # smaller requests), and of those the last PROFILED_LAUNCHES (the
+        # warmup and timed steps; the untimed pre-warm of the plain leg comes
+        # before them).
         grid = (pixels + 63) // 64 * 64
-        disp = [r for r in trace if KERNEL in r["Kernel_Name"] and int(r["Grid_Size_X"]) == grid]
+        disp = sorted((r for r in trace if KERNEL in r["Kernel_Name"] and int(r["Grid_Size_X"]) == grid),
+                      key=lambda r: int(r["Start_Timestamp"]))[-PROFILED_LAUNCHES:]
         assert disp, f"{leg} kernel missing from the trace"
         dur = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in disp]
         st = {"Name": disp[0]["Kernel_Name"], "Calls": len(dur), "MinNs": min(dur), "MaxNs": max(dur),
@@ -162,8 +170,9 @@ def summarize_profiles(d):
         per = {}
         for counter, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
             rows = counters[sub]
-            k = [float(r["Counter_Value"]) for r in rows
-                 if KERNEL in r["Kernel_Name"] and int(r["Grid_Size"]) == grid]
+            k = [float(r["Counter_Value"]) for r in sorted(
+                     (r for r in rows if KERNEL in r["Kernel_Name"] and int(r["Grid_Size"]) == grid),
+                     key=lambda r: int(r["Dispatch_Id"]))[-PROFILED_LAUNCHES:]]
             copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
             calib = float(copies[-1]["Counter_Value"])  # the 1 GiB copy runs last
             factor = (1 << 30) / (calib * 1024.0)       # bytes per counted byte
@@ -183,7 +192,8 @@ def summarize_profiles(d):
             f.write(f"# rocprofv3 kernel trace: {KERNEL.strip(':(')}, {spec['workload']}\n\n")
             f.write("Command (from the repository root, on one MI355X):\n\n    "
                     + PROFILE_CMD.format(flags="--kernel-trace --stats") + "\n\n")
-            f.write(f"Launches over the whole workload (grid of {grid} work-items) only.\n\n")
+            f.write(f"The leg's warmup and timed launches over the whole workload (grid of {grid} "
+                    f"work-items) only.\n\n")
             f.write("| kernel | calls | average ns | min ns | max ns |\n|---|---|---|---|---|\n")
             f.write(f"| {st['Name']} | {st['Calls']} | {avg_ns:.0f} | {st['MinNs']} | "
                     f"{st['MaxNs']} |\n\n")
@@ -318,6 +328,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--prewarm-s", type=float, default=0.25,
+                    help="seconds of untimed steps before the warmup steps (clock ramp)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="write profiles/ summaries from rocprofv3 output under DIR and exit")
@@ -354,6 +366,13 @@ def main():
                         outputs=("brk", "mag"), out_dtype=torch.float32, out=out)
 
     stream = torch.cuda.current_stream(dev)
+    t_warm = time.perf_counter()
+    warm_steps = 0
+    while time.perf_counter() - t_warm < args.prewarm_s:
+        step()
+        torch.cuda.synchronize()
+        warm_steps += 1
+    log(f"bench: pre-warm {warm_steps} steps in {time.perf_counter() - t_warm:.2f} s")
     log(f"bench: plain leg, warmup {args.warmup}, timing {args.steps} steps")
     tp = timed(step, args.steps, args.warmup, stream)
     log(f"bench: {tp['ms_per_step']:.4f} ms/step wall, kernel mean {tp['mean']:.4f} ms")
