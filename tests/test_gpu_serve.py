@@ -125,3 +125,41 @@ def test_admission_errors(bfm):
         r = srv.result(t)
         assert r["rc"] == bfm.E_UNSUPPORTED
         assert srv.stats()["pool_in_use"] == 0
+
+
+def test_config5_largest_requests_in_the_mix(bfm, orc):
+    """Requests at the serving workload's extremes (2048^2 and 256^2 pixels,
+    N = 600 and 200, k = 10 and 6 regressors, up to 40% NaN, FP16 storage and a
+    filled one) run together: each equals its run alone bit for bit, and sampled
+    pixels of the largest one match the oracle."""
+    from parity import compare
+    say("case serving config-5 extremes")
+    specs = [(2048 * 2048, 600, 4, 0.4, torch.float32, 1), (256 * 256, 200, 2, 0.0, torch.float32, 0),
+             (2048 * 2048, 400, 3, 0.0, torch.float16, 0), (512 * 512, 300, 3, 0.1, torch.float32, 3)]
+    reqs = []
+    for i, (P, N, order, miss, dt, mode) in enumerate(specs):
+        Y, n = payload(P, N, order, miss, 5000 + i, dt)
+        reqs.append((Y, dict(n=n, order=order, mask_mode=mode, outputs=("brk", "mag", "sigma", "status"),
+                             out_dtype=torch.float64)))
+    alone = [to_numpy(bfm.fit_monitor(Y, **kw)) for Y, kw in reqs]
+    torch.cuda.synchronize()
+    with bfm.Server(slots=4, pool_bytes=1 << 30) as srv:
+        tickets = [srv.submit(Y, **kw) for Y, kw in reqs]
+        got = [srv.result(t) for t in tickets]
+    for i, (r, a) in enumerate(zip(got, alone)):
+        assert r["rc"] == 0
+        g = to_numpy({k: r[k] for k in a})
+        for k in a:
+            np.testing.assert_array_equal(g[k], a[k], err_msg=f"request {i} {k}")
+    Y, kw = reqs[0]
+    P = Y.shape[1]
+    idx = np.unique(np.r_[np.arange(32), np.arange(P - 32, P),
+                          np.random.default_rng(1).integers(0, P, 1200)])
+    Ys = Y[:, torch.as_tensor(idx, device="cuda")].cpu().numpy()
+    o = orc.fit_monitor(Ys, n=kw["n"], order=kw["order"], mask_mode=orc.MASK_NAN, threads=0)
+    gs = {k: v[idx] for k, v in alone[0].items()}
+    diff = gs["brk"] != o["brk"]
+    assert diff.sum() <= 2, diff.sum()
+    keep = ~diff
+    say("largest request sample", compare({k: v[keep] for k, v in gs.items()},
+                                          {k: v[..., keep] for k, v in o.items()}))
