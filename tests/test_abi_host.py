@@ -200,3 +200,19 @@ def test_server_create_without_device_reports_nodevice(bfm):
     assert lib.bfm_server_create(ctypes.byref(h), 0, 4, 1 << 20) == bfm.E_NODEVICE and not h.value
     assert lib.bfm_server_create(ctypes.byref(h), 0, 0, 1 << 20) == bfm.E_INVAL
     assert lib.bfm_server_destroy(None) == 0
+
+
+def test_simulated_lambda_entry_points_reject_without_device(bfm):
+    """The critical-value entry points validate their arguments before any
+    device work: a NULL context, bad parameters and bad alpha or path counts."""
+    lib = ctypes.CDLL(bfm.LIB_PATH)
+    lib.bfm_critical_value.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                       ctypes.c_int64, ctypes.c_uint64,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
+    lib.bfm_mosum_null_sup.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                       ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+    prm = bfm.make_params(400, 200, 0, h_window=50)
+    out = ctypes.c_double()
+    assert lib.bfm_critical_value(None, ctypes.byref(prm), 0.05, 100, 0, ctypes.byref(out), None) == bfm.E_INVAL
+    assert lib.bfm_mosum_null_sup(None, ctypes.byref(prm), 0, 0, 10, None, None) == bfm.E_INVAL
+    assert "ctx" in bfm.load().bfm_last_error().decode()
