@@ -200,7 +200,8 @@ int bfm_fit_monitor(bfm_ctx *ctx, const bfm_params *prm, const float *Y, int64_t
  * the rounding of the data itself (BF16 keeps 8 significant bits, FP16 11).
  * ld and ldv count elements.  16-bit series are served by the period-blocked
  * kernels: f in {12, 23, 24} and order <= 4, and additionally on the plain path
- * a window H >= f, a full-rank history design and ld * 2 * f < 2^31, on the
+ * a window f <= H <= 160 (its workgroup's window rings take H KB of the 160 KB
+ * of LDS), a full-rank history design and ld * 2 * f < 2^31, on the
  * missing-value paths n_hist <= 8192 and ld * 4 * f < 2^31, and neither
  * observation times nor BFM_MASK_FILL; other parameter sets return
  * BFM_E_UNSUPPORTED.

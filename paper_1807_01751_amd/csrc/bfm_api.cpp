@@ -416,9 +416,11 @@ int bfm_fit_monitor_typed(bfm_ctx* ctx, const bfm_params* prm, const void* Y, in
     if (lds > ctx->max_lds)
         return fail(BFM_E_UNSUPPORTED, "window H=%d needs %zu B of LDS per workgroup (max %zu)",
                     ops.H, lds, ctx->max_lds);
-    // The period-blocked kernel addresses the F rows of a block with 32-bit offsets.
+    // The period-blocked kernel addresses the F rows of a block with 32-bit
+    // offsets, and its workgroup's window rings need H KB of LDS.
     const int64_t esize = y_dtype == BFM_Y_F32 ? 4 : 2;
-    if (ent->per.F > 0 && ld * esize * ent->per.F < ((int64_t)1 << 31)) {
+    if (ent->per.F > 0 && ld * esize * ent->per.F < ((int64_t)1 << 31) &&
+        bfm::periodic_split_lds(p.order, ent->per.F, 1, ops.H) <= ctx->max_lds) {
         bfm::PeriodicArgs a{};
         a.Y = Y;
         a.y_dtype = y_dtype;
@@ -450,7 +452,8 @@ int bfm_fit_monitor_typed(bfm_ctx* ctx, const bfm_params* prm, const void* Y, in
     }
     if (narrow)
         return fail(BFM_E_UNSUPPORTED, "a 16-bit series needs f in {12, 23, 24}, order <= %d, a "
-                    "window H >= f and ld * 2 * f < 2^31 on this path", bfm::kPeriodicMaxOrder);
+                    "window f <= H <= %zu and ld * 2 * f < 2^31 on this path", bfm::kPeriodicMaxOrder,
+                    ctx->max_lds / (bfm::kPeriodicBlock * sizeof(float)));
     const double* d = ent->dev;
     const size_t nq = ops.q.size(), nw = ops.w.size(), nb = ops.bnd.size();
     bfm::PlainArgs a{};
@@ -503,7 +506,8 @@ int split_shape(bfm_ctx* ctx, const bfm_params* prm, int32_t y_dtype, int64_t P,
     if (rc) return rc;
     const int64_t esize = y_dtype == BFM_Y_F32 ? 4 : 2;
     if (ent->per.F == 0 || !ent->ops.rank_ok || ent->ops.n <= ent->ops.p || ent->ops.H < 1 ||
-        ld * esize * ent->per.F >= ((int64_t)1 << 31))
+        ld * esize * ent->per.F >= ((int64_t)1 << 31) ||
+        bfm::periodic_split_lds(prm->order, ent->per.F, 1, ent->ops.H) > ctx->max_lds)
         return fail(BFM_E_UNSUPPORTED, "these parameters do not take the period-blocked plain kernel");
     *H = ent->ops.H;
     *F = ent->per.F;

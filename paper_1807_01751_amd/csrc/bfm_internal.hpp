@@ -17,6 +17,10 @@ constexpr int kMaxP = 2 + 2 * kMaxOrder;
 constexpr double kSigmaRelTol = 1e-6;        // DEGENERATE_SIGMA threshold
 constexpr double kRankTol = 1e-6;            // |R_jj| <= tol * sqrt(rows)
 constexpr int kPlainBlock = 64;              // threads per block (one wave), plain path
+// Threads per workgroup of the period-blocked plain kernel: four waves over 256
+// adjacent pixels, so that the row segments they read together are contiguous
+// (1 KB per row instead of 256 B; measured 2% faster at 1024x1024, N = 400).
+constexpr int kPeriodicBlock = 256;
 
 // Shared operators of the plain path, built on the host in FP64 (Section 3:
 // the pseudo-inverse M is formed once for all pixels; here its orthonormal

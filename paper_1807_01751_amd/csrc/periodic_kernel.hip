@@ -15,7 +15,7 @@ hipError_t launch_periodic_split(const PeriodicArgs& a, int order, int F, hipStr
 
 size_t periodic_split_lds(int order, int F, int split, int H)
 {
-    if (split == 1) return (size_t)H * kPlainBlock * sizeof(float);
+    if (split == 1) return (size_t)H * kPeriodicBlock * sizeof(float);
     if (split != 2 && split != 4 && split != 8) return 0;
     return split_lds_bytes(F, 2 + 2 * order, split, H);
 }

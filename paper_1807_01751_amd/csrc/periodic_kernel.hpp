@@ -42,14 +42,14 @@ template <int K, int F, bool EXPORT, typename T, bool FILL>
 // Three waves per SIMD: the LDS ring of a 50-row window allows twelve per CU.
 #define BFM_PERIODIC_OCC __attribute__((amdgpu_waves_per_eu(3)))
 #endif
-__global__ __launch_bounds__(kPlainBlock) BFM_PERIODIC_OCC
+__global__ __launch_bounds__(kPeriodicBlock) BFM_PERIODIC_OCC
 void periodic_kernel(PeriodicArgs a)
 {
     constexpr int NP = 2 + 2 * K;
     constexpr int NH = 2 * K;
-    extern __shared__ float ring[];  // H rows x kPlainBlock lanes
+    extern __shared__ float ring[];  // H rows x kPeriodicBlock lanes
     const int tid = threadIdx.x;
-    const int64_t pix = (int64_t)blockIdx.x * kPlainBlock + tid;
+    const int64_t pix = (int64_t)blockIdx.x * kPeriodicBlock + tid;
     const bool active = pix < a.P;
     const uint32_t lane = (uint32_t)(active ? pix : a.P - 1);
     const uint32_t lane_bytes = lane * (uint32_t)sizeof(T);
@@ -101,7 +101,7 @@ void periodic_kernel(PeriodicArgs a)
         [&](int u, int t, float v) {
             v = obs(v);
             hist(u, t, v);
-            myring[slot * kPlainBlock] = v;
+            myring[slot * kPeriodicBlock] = v;
             slot = slot + 1 == H ? 0 : slot + 1;
         },
         hist_pre);
@@ -180,7 +180,7 @@ void periodic_kernel(PeriodicArgs a)
     // Window sum over the last H history rows (all ring slots), minus the trend
     // part at t = n - 1.
     double S = 0.0;
-    for (int s = 0; s < H; ++s) S += (double)myring[s * kPlainBlock] - c;
+    for (int s = 0; s < H; ++s) S += (double)myring[s * kPeriodicBlock] - c;
     double Sp = S - Lc - gamma * (double)n;
 
     // ---- monitoring period (Eq. 3, Eq. 4) ----
@@ -197,7 +197,7 @@ void periodic_kernel(PeriodicArgs a)
             if (u >= lo_ && u < hi_) {
                 int s = s0 + (u - lo_);
                 s -= s >= H ? H : 0;
-                vo[u] = myring[s * kPlainBlock];
+                vo[u] = myring[s * kPeriodicBlock];
             }
         }
         slot = s0 + (hi_ - lo_);
@@ -212,7 +212,7 @@ void periodic_kernel(PeriodicArgs a)
     };
     auto row = [&](int u, int t, float v, double thr) {
         v = obs(v);
-        myring[wslot * kPlainBlock] = v;
+        myring[wslot * kPeriodicBlock] = v;
         wslot = wslot + 1 == H ? 0 : wslot + 1;
         Sp += ((double)v - (double)vo[u]) - gamma;
         const double num = Sp - Pw[u];
@@ -560,12 +560,12 @@ hipError_t launch_split_ns(const PeriodicArgs& a, int order, int F, hipStream_t 
 template <int K, int F, typename T, bool FILL>
 hipError_t launch_kf(const PeriodicArgs& a, hipStream_t stream)
 {
-    const dim3 grid((unsigned)((a.P + kPlainBlock - 1) / kPlainBlock));
-    const size_t lds = (size_t)a.H * kPlainBlock * sizeof(float);
+    const dim3 grid((unsigned)((a.P + kPeriodicBlock - 1) / kPeriodicBlock));
+    const size_t lds = (size_t)a.H * kPeriodicBlock * sizeof(float);
     if (a.resid || a.mosum)
-        hipLaunchKernelGGL((periodic_kernel<K, F, true, T, FILL>), grid, dim3(kPlainBlock), lds, stream, a);
+        hipLaunchKernelGGL((periodic_kernel<K, F, true, T, FILL>), grid, dim3(kPeriodicBlock), lds, stream, a);
     else
-        hipLaunchKernelGGL((periodic_kernel<K, F, false, T, FILL>), grid, dim3(kPlainBlock), lds, stream, a);
+        hipLaunchKernelGGL((periodic_kernel<K, F, false, T, FILL>), grid, dim3(kPeriodicBlock), lds, stream, a);
     return hipGetLastError();
 }
 

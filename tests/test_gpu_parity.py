@@ -238,3 +238,18 @@ def test_config2_full_size_sampled(bfm, orc):
     brk_rate = (g["brk"] >= 0).mean()
     say("config2 break rate", brk_rate)
     assert 0.15 < brk_rate < 0.35
+
+
+def test_window_longer_than_the_periodic_workgroup_lds(bfm, orc):
+    """f = 23 with H = 180 rows: the period-blocked kernel's workgroup would need
+    180 KB of LDS for its window rings, so the table-driven kernel serves it."""
+    say("case long window P=3000 N=800 n=400 H=180")
+    Y = series(3000, 800, 400, seed=41)
+    g = to_numpy(bfm.fit_monitor(Y, n=400, h=0.45, outputs=ALL))
+    o = orc.fit_monitor(Y.cpu().numpy(), n=400, h=0.45, threads=0)
+    rep = compare(g, o, bnd=bnd_of(800, 400, 2.5))
+    say(rep)
+    assert rep["not_ok"] == 0
+    with pytest.raises(bfm.BfmError) as e:
+        bfm.fit_monitor(Y.to(torch.float16), n=400, h=0.45)
+    assert e.value.code == bfm.E_UNSUPPORTED
