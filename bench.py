@@ -85,10 +85,12 @@ def log(*a):
 
 
 def kernel_sha():
-    """Hash of the library sources (a change invalidates the stored counters)."""
+    """Hash of the kernel sources, the .hip translation units and the headers
+    they include (a change invalidates the stored counters; host-only .cpp
+    files do not take part)."""
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
+        if name.endswith((".hip", ".hpp")):
             with open(os.path.join(CSRC, name), "rb") as f:
                 h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]

@@ -389,6 +389,21 @@ int bfm_server_destroy(bfm_server *s);
  */
 int bfm_host_operators(const bfm_params *prm, double *q, double *w, double *bnd, double *bmap);
 
+/*
+ * Device memory the library holds for a call of bfm_fit_monitor(_typed) with
+ * these parameters over P pixels, for admission by HBM footprint (no device
+ * needed).  The library keeps no per-pixel workspace: a call streams Y once
+ * and writes the caller's outputs, so the footprint is the operator block it
+ * builds once per parameter set (Section 3 forms the shared matrix once for
+ * all pixels) and caches in the context until bfm_destroy: the table rows of
+ * the plain path (and those of the period-blocked kernel when f is 12, 23 or
+ * 24), or the design and product tables of the missing-value path.  *out gets
+ * that size in bytes, whatever P.  The caller's Y and outputs are not counted
+ * (bfm_request_bytes gives a serving request's outputs).
+ * Errors: BFM_E_INVAL (bad parameters, out NULL), BFM_E_LAYOUT.
+ */
+int bfm_workspace_bytes(const bfm_params *prm, int64_t P, size_t *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,7 +36,7 @@ EXPORTS = ("bfm_version", "bfm_last_error", "bfm_check_params", "bfm_create", "b
            "bfm_fit_monitor", "bfm_fit_monitor_typed", "bfm_host_operators", "bfm_request_bytes",
            "bfm_server_create", "bfm_server_submit", "bfm_server_wait", "bfm_server_release",
            "bfm_server_take", "bfm_autotune", "bfm_tune_set", "bfm_mosum_null_sup",
-           "bfm_critical_value",
+           "bfm_critical_value", "bfm_workspace_bytes",
            "bfm_server_get_stats", "bfm_server_destroy")
 WANT = {"mag": 1, "sigma": 2, "status": 4, "beta": 8, "resid": 16, "mosum": 32}
 
@@ -133,6 +133,7 @@ def load():
                                  ctypes.POINTER(ctypes.c_double)]
     lib.bfm_tune_set.argtypes = [vp, P_, ctypes.c_int32, i64, ctypes.c_int32]
     lib.bfm_mosum_null_sup.argtypes = [vp, P_, ctypes.c_uint64, i64, i64, vp, vp]
+    lib.bfm_workspace_bytes.argtypes = [P_, i64, ctypes.POINTER(ctypes.c_size_t)]
     lib.bfm_critical_value.argtypes = [vp, P_, ctypes.c_double, i64, ctypes.c_uint64,
                                        ctypes.POINTER(ctypes.c_double), vp]
     R_ = ctypes.POINTER(Request)
@@ -177,6 +178,13 @@ def make_params(N: int, n: int, order: int = 3, freq: float = 23.0, h: float = 0
 def check_params(prm: Params, P: int, ld: int) -> None:
     """bfm_check_params: validation only, no device."""
     _raise(load().bfm_check_params(ctypes.byref(prm), int(P), int(ld)))
+
+
+def workspace_bytes(prm: Params, P: int) -> int:
+    """bfm_workspace_bytes: device bytes the library caches for these parameters."""
+    out = ctypes.c_size_t()
+    _raise(load().bfm_workspace_bytes(ctypes.byref(prm), int(P), ctypes.byref(out)))
+    return out.value
 
 
 def host_operators(prm: Params):

@@ -342,6 +342,31 @@ int bfm_destroy(bfm_ctx* ctx)
     return BFM_SUCCESS;
 }
 
+int bfm_workspace_bytes(const bfm_params* prm, int64_t P, size_t* out)
+{
+    int rc = check(prm, P, P);
+    if (rc) return rc;
+    if (!out) return fail(BFM_E_INVAL, "out is NULL");
+    size_t doubles = 0;
+    if (prm->mask_mode == BFM_MASK_NAN || prm->mask_mode == BFM_MASK_EXPLICIT) {
+        bfm::MaskedOps ops;
+        bfm::build_masked_ops(*prm, &ops);
+        doubles = ops.x.size() + ops.g.size() + ops.ph.size();
+    } else {
+        bfm::PlainOps ops;
+        bfm::build_plain_ops(*prm, &ops);
+        doubles = ops.q.size() + ops.w.size() + ops.bnd.size() + ops.bmap.size();
+        const int F = bfm::periodic_period(*prm, ops);
+        if (F > 0) {
+            bfm::PeriodicOps per;
+            bfm::build_periodic_ops(*prm, ops, F, &per);
+            doubles += per.rt.size() + per.ri.size() + per.hh.size() + per.wh.size() + ops.bnd.size();
+        }
+    }
+    *out = doubles * sizeof(double);
+    return BFM_SUCCESS;
+}
+
 int bfm_host_operators(const bfm_params* prm, double* q, double* w, double* bnd, double* bmap)
 {
     int rc = check(prm, 0, 0);

@@ -216,3 +216,22 @@ def test_simulated_lambda_entry_points_reject_without_device(bfm):
     assert lib.bfm_critical_value(None, ctypes.byref(prm), 0.05, 100, 0, ctypes.byref(out), None) == bfm.E_INVAL
     assert lib.bfm_mosum_null_sup(None, ctypes.byref(prm), 0, 0, 10, None, None) == bfm.E_INVAL
     assert "ctx" in bfm.load().bfm_last_error().decode()
+
+
+def test_workspace_bytes_is_the_cached_operator_block(bfm):
+    """The device footprint of a parameter set: the operator tables, counted
+    from their shapes (N=400, n=200, k=3, H=50, f=23: q N x p, w (N-n) x p, the
+    boundary, bmap p x p, and the period-blocked tables R^-T, R^-1, two F x 2k
+    harmonic tables and the boundary again), independent of the pixel count."""
+    N, n, k, F = 400, 200, 3, 23
+    p, M = 2 + 2 * k, N - n
+    plain = N * p + M * p + M + p * p
+    periodic = 2 * p * p + 2 * F * 2 * k + M
+    prm = bfm.make_params(N, n, k)
+    assert bfm.workspace_bytes(prm, 1 << 20) == 8 * (plain + periodic)
+    assert bfm.workspace_bytes(prm, 7) == 8 * (plain + periodic)
+    assert bfm.workspace_bytes(bfm.make_params(N, n, k, freq=22.5), 100) == 8 * plain
+    masked = bfm.workspace_bytes(bfm.make_params(N, n, k, mask_mode=bfm.MASK_NAN), 100)
+    assert masked == 8 * (N * p + n * (2 + 6 * k) + F * 4 * k)
+    with pytest.raises(bfm.BfmError):
+        bfm.workspace_bytes(bfm.make_params(N, N, k), 100)
