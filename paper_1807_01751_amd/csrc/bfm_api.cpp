@@ -166,6 +166,8 @@ void drop_if_stale(Map& m, const bfm_ctx::Key& key, const bfm_params& p)
     if (it->second.times.size() == (size_t)p.n_obs &&
         std::memcmp(it->second.times.data(), p.times, (size_t)p.n_obs * sizeof(double)) == 0)
         return;
+    // Kernels launched earlier with this block may still run on some stream.
+    (void)hipDeviceSynchronize();
     (void)hipFree(it->second.dev);
     if constexpr (std::is_same_v<typename Map::mapped_type, bfm_ctx::Entry>)
         if (it->second.pdev) (void)hipFree(it->second.pdev);
