@@ -365,7 +365,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "the pixel-sharded multi-GPU form is described in DESIGN.md and not run here.",
+              "pixels are independent, so several GPUs would each take a range of pixels with "
+              "no traffic between them; that form is not run here.",
               file=sys.stderr)
         sys.exit(2)
 
