@@ -71,3 +71,27 @@ def test_autotune_picks_a_split(bfm):
     with pytest.raises(bfm.BfmError) as e:
         bfm.tune_set(Y, 2, n=114, freq=22.5)
     assert e.value.code == bfm.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("mode", ["plain", "fill"])
+def test_default_split_on_a_long_series_over_few_pixels(bfm, orc, mode):
+    """4096 pixels x 1000 rows with no tuning: the default rule gives the plain
+    path eight waves per 64 pixels (a tile of at most one wave per compute unit
+    over N >= 512); filling always streams one wave per 64 pixels.  Both match
+    the oracle."""
+    from paper_1807_01751_amd.synth import apply_missing, make_missing, make_series, split_rate
+    say(f"case default split {mode} P=4096 N=1000 n=500 h=0.1")
+    P, N, n, h = 4096, 1000, 500, 0.1
+    Y, _ = make_series(P, N, n, 3, seed=91, device="cuda")
+    kw = dict(n=n, h=h)
+    if mode == "fill":
+        r = split_rate(0.1)
+        Y = apply_missing(Y, make_missing(N, P, iid=r, runs=r, seed=92, device="cuda"))
+        g = to_numpy(bfm.fit_monitor(Y, mask_mode=bfm.MASK_FILL, outputs=LEAN, **kw))
+        o = orc.fit_monitor(Y.cpu().numpy(), mask_mode=orc.MASK_FILL, threads=0, **kw)
+    else:
+        g = to_numpy(bfm.fit_monitor(Y, outputs=LEAN, **kw))
+        o = orc.fit_monitor(Y.cpu().numpy(), threads=0, **kw)
+    rep = compare(g, o, bnd=bnd_of(N, n, 2.5))
+    say(rep)
+    assert rep["not_ok"] == 0
