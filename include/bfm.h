@@ -73,7 +73,8 @@ extern "C" {
 /* per-pixel status */
 #define BFM_ST_OK 0
 #define BFM_ST_NONFINITE 1        /* NaN/Inf among the used observations     */
-#define BFM_ST_INSUFFICIENT 2     /* n_v <= p, or window H < 1 or H > n_v    */
+#define BFM_ST_INSUFFICIENT 2     /* n_v <= p, or window H < 1 or H > n_v,
+                                     or nothing finite to fill (MASK_FILL)   */
 #define BFM_ST_RANK_DEFICIENT 3   /* history design rank deficient           */
 #define BFM_ST_DEGENERATE_SIGMA 4 /* sigma <= 1e-6 * max |y| over history    */
 #define BFM_ST_NO_MONITOR 5       /* no used observation after the history   */
