@@ -163,3 +163,29 @@ def test_config5_largest_requests_in_the_mix(bfm, orc):
     keep = ~diff
     say("largest request sample", compare({k: v[keep] for k, v in gs.items()},
                                           {k: v[..., keep] for k, v in o.items()}))
+
+
+def test_requests_with_observation_times(bfm):
+    """Requests of the same shape with different observation times (day
+    numbers, f = 365) in one mix: each gets the operators of its own times and
+    the results of its run alone."""
+    from paper_1807_01751_amd.synth import acquisition_days, make_series
+    say("case serving with observation times")
+    reqs = []
+    for i in range(3):
+        days = acquisition_days(288, seed=40 + i)
+        Y, _ = make_series(50000, 288, 144, 3, freq=365.0, times=days, trend=2e-5, seed=50 + i,
+                           device="cuda")
+        reqs.append((Y, dict(n=144, order=3, freq=365.0, h_window=72, times=days,
+                             outputs=("brk", "mag", "sigma", "status"), out_dtype=torch.float64)))
+    alone = [to_numpy(bfm.fit_monitor(Y, **kw)) for Y, kw in reqs]
+    torch.cuda.synchronize()
+    with bfm.Server(slots=3, pool_bytes=1 << 26) as srv:
+        tickets = [srv.submit(Y, **kw) for Y, kw in reqs]
+        got = [srv.result(t) for t in tickets]
+    for i, (r, a) in enumerate(zip(got, alone)):
+        assert r["rc"] == 0
+        g = to_numpy({k: r[k] for k in a})
+        for k in a:
+            np.testing.assert_array_equal(g[k], a[k], err_msg=f"request {i} {k}")
+    assert not np.array_equal(alone[0]["sigma"], alone[1]["sigma"])
