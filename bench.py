@@ -77,7 +77,7 @@ FILL_MISSING = 0.10
 LAMBDA_PATHS = 1 << 20
 PROFILE_CMD = ("rocprofv3 {flags} -f csv -d <dir> -o run -- python3 bench.py --steps 10 "
                "--warmup 2 --no-cpu-baseline --copy-calibration")
-PROFILED_LAUNCHES = 12  # --warmup 2 + --steps 10 of PROFILE_CMD
+PROFILED_LAUNCHES = 20  # the --steps 10 timed launches of PROFILE_CMD and the 10 of the latency pass
 
 
 def log(*a):
@@ -194,8 +194,8 @@ def summarize_profiles(d):
             f.write(f"# rocprofv3 kernel trace: {KERNEL.strip(':(')}, {spec['workload']}\n\n")
             f.write("Command (from the repository root, on one MI355X):\n\n    "
                     + PROFILE_CMD.format(flags="--kernel-trace --stats") + "\n\n")
-            f.write(f"The leg's warmup and timed launches over the whole workload (grid of {grid} "
-                    f"work-items) only.\n\n")
+            f.write(f"The leg's timed and latency-pass launches over the whole workload (grid of "
+                    f"{grid} work-items) only.\n\n")
             f.write("| kernel | calls | average ns | min ns | max ns |\n|---|---|---|---|---|\n")
             f.write(f"| {st['Name']} | {st['Calls']} | {avg_ns:.0f} | {st['MinNs']} | "
                     f"{st['MaxNs']} |\n\n")
@@ -216,24 +216,34 @@ def summarize_profiles(d):
 
 
 def timed(step, steps, warmup, stream):
-    """Warm up, then time ``steps`` calls: wall clock over all of them and HIP
-    events around each launch on the stream the kernel runs on."""
+    """Warm up, then time exactly ``steps`` calls back to back: wall clock over
+    all of them, and two HIP events on the stream the kernel runs on around the
+    whole region (their span / steps is the mean launch duration).  Per-launch
+    latencies (p50, p99) come from a separate pass of as many calls, each
+    bracketed by its own events (which add a short gap between launches, so they
+    are kept out of the timed region)."""
     import torch
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
-    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    for a, b in ev:
-        a.record(stream)
+    a.record(stream)
+    for _ in range(steps):
         step()
-        b.record(stream)
+    b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    lat = sorted(a.elapsed_time(b) for a, b in ev)  # ms, per launch
-    return {"ms_per_step": wall * 1e3 / steps, "mean": sum(lat) / len(lat),
+    mean = a.elapsed_time(b) / steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for x, y in ev:
+        x.record(stream)
+        step()
+        y.record(stream)
+    torch.cuda.synchronize()
+    lat = sorted(x.elapsed_time(y) for x, y in ev)  # ms, per launch
+    return {"ms_per_step": wall * 1e3 / steps, "mean": mean,
             "p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, int(round(0.99 * (len(lat) - 1))))]}
 
 
