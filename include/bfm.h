@@ -241,11 +241,16 @@ int bfm_tune_set(bfm_ctx *ctx, const bfm_params *prm, int32_t y_dtype, int64_t P
  * horizon N/n.  These entry points simulate the MOSUM of Eq. 3 under no change
  * at the resolution of the series (n_hist, n_obs and the window H of prm; its
  * other fields are validated but unused): with i.i.d. standard normal errors
- * z_1..z_N and the intercept model (whose residual MOSUM has the same limiting
- * process as the season-trend model's, W(t) - W(t-h) - h W(1)),
+ * z_1..z_N and the intercept-only model,
  *   M_k = (sum_{i=k-H+1..k} z_i - (H/n) sum_{i=1..n} z_i) / sqrt(n),
  *   S   = max_{k=n+1..N} |M_k| / sqrt(log+(k/n)),
- * and a path crosses lambda sqrt(log+) iff S > lambda.  The normals of path q
+ * and a path crosses lambda sqrt(log+) iff S > lambda.  This is the convention
+ * of the method the paper cites for lambda: critical values of the process
+ * W(t) - W(t-h) - h W(1) (the limit of M, and of the residual MOSUM of models
+ * whose regressors have a stable second-moment matrix).  It is not an exact
+ * level-alpha value for the season-trend model of Eq. 2, whose trend slope
+ * error adds a term of order one to the limit.  The discrete sup over n steps
+ * per unit of time is about 0.5826 sqrt(2/n) below the continuous one.  The normals of path q
  * come from Philox4x64-10 (Salmon et al., SC 2011) with key (seed, 0) and
  * counter (j, q, 0, 0) for steps 4j+1..4j+4, through the Box-Muller transform
  * of the uniforms ((w >> 11) + 1/2) 2^-53: results depend only on (seed, q),

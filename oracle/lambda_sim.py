@@ -5,14 +5,12 @@ TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
 leg of the benchmark call this module; the GPU library never does, and it shares
 no code with it.
 
-Section 2.1 chooses lambda so that, when nothing changes, the MOSUM crosses the
-boundary lambda sqrt(log+(t/n)) with probability alpha; lambda depends on alpha,
-the window h and the horizon N/n and is found by simulation.  This module
-simulates the MOSUM of Eq. 3 under no change at the resolution of the series:
-with i.i.d. standard normal errors z_1..z_N and the intercept model (whose
-residual MOSUM has the same limit as that of the season-trend model: the
-limiting process is W(t) - W(t-h) - h W(1) of a standard Brownian motion W, t
-in units of the history length),
+Section 2.1 chooses lambda so that, when nothing changes, the MOSUM crosses
+the boundary lambda sqrt(log+(t/n)) with probability alpha; lambda depends on
+alpha, the window h and the horizon N/n and is found by simulation, following
+the method the paper cites for it.  This module simulates the MOSUM of Eq. 3
+under no change at the resolution of the series, with i.i.d. standard normal
+errors z_1..z_N and the intercept-only model:
 
     M_k = ( sum_{i=k-H+1..k} z_i  -  (H/n) sum_{i=1..n} z_i ) / sqrt(n),
     S   = max_{k=n+1..N} |M_k| / sqrt(log+(k/n)),
@@ -20,6 +18,19 @@ in units of the history length),
 and a path crosses lambda sqrt(log+(k/n)) iff S > lambda.  lambda is the
 ceil((1 - alpha) * paths)-th smallest S: at most a share alpha of the paths
 cross it.
+
+What this lambda is: M is the intercept model's residual MOSUM, whose limit
+(t in units of the history length) is W(t) - W(t-h) - h W(1) for a standard
+Brownian motion W.  The cited method takes its critical values from that
+limiting process, which is also the limit for regressors with a stable
+second-moment matrix.  The season-trend model of Eq. 2 is not such a model:
+the error of the fitted slope, extrapolated over the monitoring period, adds a
+term of order one to its residual MOSUM's limit.  So lambda here is the
+method's convention, not an exact level-alpha critical value for Eq. 2.  The
+discrete sup over n steps per unit of time falls short of the continuous one
+by about 0.5826 sqrt(2/n) (Siegmund's correction for a random walk whose steps
+have variance 2/n); with that correction the simulated lambda for alpha =
+0.05, h = 1/2, N/n = 2 agrees with the value 2.39 printed in Section 4.3.
 
 Random numbers: Philox4x64-10 (Salmon, Moraes, Dror and Shaw, "Parallel random
 numbers: as easy as 1, 2, 3", SC 2011) with key (seed, 0) and counter
@@ -87,22 +98,33 @@ def normals(seed: int, paths, count: int) -> np.ndarray:
     return z.reshape(4 * nb, len(paths))[:count]
 
 
-def mosum_paths(n: int, N: int, H: int, seed: int, paths) -> np.ndarray:
-    """M_k for k = n+1..N (rows) of each path index (columns), by the
-    definition: window sums of z minus (H/n) times the history sum, over
-    sqrt(n)."""
-    z = normals(seed, paths, N)
+def mosum_of_normals(n: int, N: int, H: int, z) -> np.ndarray:
+    """M_k for k = n+1..N (rows) of each path (column of ``z``, the normals
+    z_1..z_N of the path in its rows), by the definition: window sums of z
+    minus (H/n) times the history sum, over sqrt(n)."""
+    z = np.asarray(z, np.float64)
     C = np.vstack([np.zeros((1, z.shape[1])), np.cumsum(z, axis=0)])  # C[k] = z_1 + .. + z_k
     k = np.arange(n + 1, N + 1)
     return (C[k] - C[k - H] - (H / n) * C[n]) / math.sqrt(n)
 
 
-def sup_statistic(n: int, N: int, H: int, seed: int, paths) -> np.ndarray:
-    """S = max_k |M_k| / sqrt(log+(k/n)) per path."""
-    M = mosum_paths(n, N, H, seed, paths)
+def sup_of_normals(n: int, N: int, H: int, z) -> np.ndarray:
+    """S = max_k |M_k| / sqrt(log+(k/n)) of each path (column of ``z``)."""
+    M = mosum_of_normals(n, N, H, z)
     t = np.arange(n + 1, N + 1) / n
     b = np.sqrt(np.where(t <= math.e, 1.0, np.log(np.maximum(t, 1.0))))
     return (np.abs(M) / b[:, None]).max(axis=0)
+
+
+def mosum_paths(n: int, N: int, H: int, seed: int, paths) -> np.ndarray:
+    """M_k for k = n+1..N (rows) of each path index (columns), on the normals
+    of the counter-based generator above."""
+    return mosum_of_normals(n, N, H, normals(seed, paths, N))
+
+
+def sup_statistic(n: int, N: int, H: int, seed: int, paths) -> np.ndarray:
+    """S = max_k |M_k| / sqrt(log+(k/n)) per path index."""
+    return sup_of_normals(n, N, H, normals(seed, paths, N))
 
 
 def quantile_rank(alpha: float, paths: int) -> int:

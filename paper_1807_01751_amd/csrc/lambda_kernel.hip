@@ -4,8 +4,9 @@
 // lambda sqrt(log+(t/n)) with probability alpha; it depends on alpha, the window
 // and the horizon N/n and is found by simulation.  One lane simulates one path
 // of the MOSUM under no change at the resolution of the series (i.i.d. standard
-// normal errors, intercept model: the residual MOSUM of the season-trend model
-// has the same limiting process, W(t) - W(t-h) - h W(1)):
+// normal errors, intercept-only model; its limit W(t) - W(t-h) - h W(1) is the
+// process the cited method takes its critical values from, a convention rather
+// than the exact limit for the trend regressor of Eq. 2):
 //
 //   M_k = (sum of z over the window (k-H, k] - (H/n) sum_{i<=n} z_i) / sqrt(n),
 //   S   = max_{k=n+1..N} |M_k| / sqrt(log+(k/n)),

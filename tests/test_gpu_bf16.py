@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 import torch
 
-from parity import compare, to_numpy
+from parity import compare, to_numpy, used_history
 
 pytestmark = pytest.mark.gpu
 
@@ -133,10 +133,7 @@ def test_bf16_full_tile_sampled(bfm, orc):
     Ys = Yb[:, torch.as_tensor(idx, device="cuda")].float().cpu().numpy()
     o = orc.fit_monitor(Ys, n=n, threads=0)
     gs = {k: v[idx] for k, v in g.items()}
-    diff = gs["brk"] != o["brk"]
-    assert diff.sum() <= 1, diff.sum()
-    keep = ~diff
-    rep = compare({k: v[keep] for k, v in gs.items()}, {k: v[..., keep] for k, v in o.items()})
+    rep = compare(gs, o, bnd=bnd_of(N, n, 2.5))
     say("bf16 full tile sample", rep)
 
 
@@ -170,31 +167,31 @@ def test_narrow_storage_accuracy_against_float32_series(bfm, dt, agree_min, mo_m
 
 @pytest.mark.parametrize("order", [3, 4], ids=["k8", "k10"])
 def test_config4_full_size_sampled(bfm, orc, order):
-    """4096x4096 pixels (16.8M), N = 512, n = 256, 10% NaN, stored as FP16 and
-    BF16 (the masked period-blocked kernel, FP64 arithmetic): sampled pixels
-    against the oracle on the decoded values, and break agreement with the
-    float32 series reported."""
+    """4096x4096 pixels (16.8M), N = 512, n = 256, 10% NaN (the masked
+    period-blocked kernel, FP64 arithmetic), as float32 and stored as FP16 and
+    BF16: sampled pixels of each against the oracle on the values the kernel
+    read, and the break agreement of the 16-bit runs with the float32 one."""
     say(f"case config-4 full size order={order} P=16777216 N=512")
     from paper_1807_01751_amd.synth import apply_missing, make_missing, make_series, split_rate
     P, N, n = 1 << 24, 512, 256
     Y, _ = make_series(P, N, n, order, seed=90 + order, device="cuda")
     r = split_rate(0.1)
     Y = apply_missing(Y, make_missing(N, P, iid=r, runs=r, seed=91, device="cuda"))
-    a = to_numpy(bfm.fit_monitor(Y, n=n, order=order, mask_mode=bfm.MASK_NAN, outputs=("brk",)))
     rng = np.random.default_rng(7)
     idx = np.unique(np.r_[np.arange(32), np.arange(P - 32, P), rng.integers(0, P, 1500)])
     sel = torch.as_tensor(idx, device="cuda")
+    lean = ("brk", "mag", "sigma", "status")
+    a = to_numpy(bfm.fit_monitor(Y, n=n, order=order, mask_mode=bfm.MASK_NAN, outputs=lean))
+    Ys = Y[:, sel].cpu().numpy()
+    o = orc.fit_monitor(Ys, n=n, order=order, mask_mode=orc.MASK_NAN, threads=0)
+    rep = compare({k: v[idx] for k, v in a.items()}, o, lam=2.5, n_v=used_history(Ys, n))
+    say(f"config 4 float32 order {order}: sample {rep}")
     for dt in (torch.float16, torch.bfloat16):
         Yb = Y.to(dt)
-        g = to_numpy(bfm.fit_monitor(Yb, n=n, order=order, mask_mode=bfm.MASK_NAN,
-                                     outputs=("brk", "mag", "sigma", "status")))
-        o = orc.fit_monitor(Yb[:, sel].float().cpu().numpy(), n=n, order=order,
-                            mask_mode=orc.MASK_NAN, threads=0)
-        gs = {k: v[idx] for k, v in g.items()}
-        diff = gs["brk"] != o["brk"]
-        assert diff.sum() <= 2, diff.sum()
-        keep = ~diff
-        rep = compare({k: v[keep] for k, v in gs.items()}, {k: v[..., keep] for k, v in o.items()})
+        g = to_numpy(bfm.fit_monitor(Yb, n=n, order=order, mask_mode=bfm.MASK_NAN, outputs=lean))
+        Ysb = Yb[:, sel].float().cpu().numpy()
+        o = orc.fit_monitor(Ysb, n=n, order=order, mask_mode=orc.MASK_NAN, threads=0)
+        rep = compare({k: v[idx] for k, v in g.items()}, o, lam=2.5, n_v=used_history(Ysb, n))
         agree = float((g["brk"] == a["brk"]).mean())
         say(f"config 4 {dt} order {order}: sample {rep}; break agreement with float32 {agree:.5f}")
         assert agree > (0.9 if dt == torch.bfloat16 else 0.98)

@@ -53,35 +53,14 @@ def run_both(bfm, orc, Y, *, n, order=3, freq=23.0, h=0.25, h_window=0, lam=2.5,
     return to_numpy(g), o
 
 
-def masked_margins(o, used_hist, lam, pixels):
-    """Relative distance of |MO| to the boundary at each pixel's compacted positions
-    (Eq. 4 with u / n_v), minimised over the monitoring period (oracle's MO)."""
-    out = []
-    for i in pixels:
-        mo = o["mosum"][:, i]
-        fin = np.isfinite(mo)
-        nv = used_hist[i]
-        u1 = nv + np.cumsum(fin)[fin]  # 1-based compacted positions of observed values
-        x = u1 / nv
-        b = lam * np.sqrt(np.where(x <= np.e, 1.0, np.log(np.maximum(x, 1.0))))
-        out.append(np.min(np.abs(np.abs(mo[fin]) - b) / b) if fin.any() else np.inf)
-    return np.array(out)
-
-
 def check(g, o, lam, used_hist=None):
-    """Parity.  Pixels whose break index differs must be marginal: their MOSUM comes
-    within 1e-8 (relative) of the boundary at some observed monitoring position."""
-    diff = np.nonzero(g["brk"] != o["brk"])[0]
-    keep = np.ones(len(g["brk"]), bool)
-    if len(diff):
-        assert used_hist is not None, "break indices differ"
-        m = masked_margins(o, used_hist, lam, diff)
-        assert (m < 1e-8).all(), (diff, m)
-        keep[diff] = False
-    sel = lambda d: {k: v[..., keep] for k, v in d.items()}
-    rep = compare(sel(g), sel(o))
-    rep["marginal"] = int(len(diff))
-    return rep
+    """Parity (tests/parity.py): every OK pixel on every quantity; a pixel whose
+    break index differs must be marginal, its MOSUM within 1e-8 (relative) of the
+    boundary of Eq. 4 at compacted positions (u / n_v) at some observed monitoring
+    position up to the later of the two break indices."""
+    if used_hist is None:
+        return compare(g, o)
+    return compare(g, o, lam=lam, n_v=used_hist)
 
 
 def hist_count(Y, n, valid=None):

@@ -107,3 +107,66 @@ def test_lambda_grows_with_confidence_and_horizon(lam):
     l2 = lam.critical_value(0.05, n, 2 * n, H, paths, seed=1)
     l3 = lam.critical_value(0.05, n, 4 * n, H, paths, seed=1)
     assert l1 < l2 and l2 < l3 + 0.02
+
+
+def _sup_sample(lam, n, paths, chunk=5000, seed=20180704):
+    """S of ``paths`` simulated paths at resolution n (N = 2n, H = n/2), on
+    normals from numpy's SFC64 generator (one stream per chunk, in threads): the
+    statistic and the quantile are the oracle's, only the normal source is a
+    faster library one."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    N, H = 2 * n, n // 2
+    seqs = np.random.SeedSequence(seed).spawn(paths // chunk)
+
+    def one(ss):
+        z = np.random.Generator(np.random.SFC64(ss)).standard_normal((chunk, N))
+        return lam.sup_of_normals(n, N, H, z.T)
+
+    with ThreadPoolExecutor(8) as ex:
+        return np.sort(np.concatenate(list(ex.map(one, seqs))))
+
+
+def test_critical_value_matches_section_4_3(lam):
+    """Section 4.3 prints the boundary 2.39 for alpha = 0.05, h = 72/144 = 1/2 and
+    N/n = 288/144 = 2 (where Eq. 4 is flat, so the boundary is lambda).
+
+    Bound, derived:
+      - Monte Carlo: with m = 2e5 paths the true (1 - alpha) quantile of the
+        simulated S lies between the order statistics of rank
+        r -/+ 3 sqrt(m alpha (1 - alpha)) (binomial 3-sigma band, free of the
+        distribution of S).
+      - Resolution: the printed value is itself a simulated quantile of the
+        same process at a resolution the paper does not state.  The discrete
+        sup over n steps per unit of time falls short of the continuous one by
+        rho = 0.5826 sqrt(2/n) (Siegmund's corrected diffusion approximation;
+        the constant is -zeta(1/2)/sqrt(2 pi) for a random walk, whose steps
+        have variance 2/n here), with a remainder of order 1/n taken as at most
+        c2 = 0.003 at n >= 500.  So any resolution from n = 2000 up to the
+        continuum gives a value between the band at n = 2000 and that band
+        raised by rho.
+      - The printed value stands for [2.385, 2.395] (tests/golden).
+    The printed interval must meet [band_lo(2000) - c2, band_hi(2000) + rho +
+    c2].  The correction itself is checked: the corrected bands at n = 500 and
+    n = 2000 must overlap."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                    "critical_value_section_4_3.json")))
+    half = 0.5 * 10.0 ** -g["printed_decimals"]
+    printed_lo, printed_hi = g["lambda_printed"] - half, g["lambda_printed"] + half
+    assert (g["alpha"], g["h_over_n"], g["N_over_n"]) == (0.05, 0.5, 2.0)
+    alpha, m, c2 = 0.05, 200_000, 0.003
+    r = lam.quantile_rank(alpha, m)
+    d = math.ceil(3 * math.sqrt(m * alpha * (1 - alpha)))
+    siegmund = 1.4603545088095868 / math.sqrt(2 * math.pi)  # -zeta(1/2) / sqrt(2 pi)
+    bands = {}
+    for n in (500, 2000):
+        S = _sup_sample(lam, n, m)
+        bands[n] = (S[r - 1 - d], S[r - 1], S[r - 1 + d], siegmund * math.sqrt(2.0 / n))
+    print("lambda(0.05, h=1/2, N/n=2) bands (lo, mid, hi, rho):", bands)
+    lo, mid, hi, rho = bands[2000]
+    assert lo - c2 <= printed_hi and hi + rho + c2 >= printed_lo, bands
+    lo5, _, hi5, rho5 = bands[500]
+    assert lo5 + rho5 - c2 <= hi + rho and lo + rho - c2 <= hi5 + rho5, bands
+    assert abs(mid - g["lambda_printed"]) < 0.02 and abs(mid + rho - g["lambda_printed"]) < 0.02, bands
