@@ -30,8 +30,12 @@ MUTANTS = [
      "int H = prm->h_window > 0 ? prm->h_window : (int)floor(prm->h_frac * (double)n);"),
     ("0-based trend column", "x[1] = (double)t;", "x[1] = (double)(t - 1);"),
     ("sin and cos swapped", "x[2 * j] = sin(ang);", "x[2 * j] = cos(ang) + 0.0 * sin(ang);"),
-    ("harmonic j+1", "double ang = 2.0 * M_PI * (double)j * (double)t / f;",
-     "double ang = 2.0 * M_PI * (double)(j + 1) * (double)t / f;"),
+    ("harmonic j+1", "double ang = 2.0 * M_PI * fmod((double)j * (double)t, f) / f;",
+     "double ang = 2.0 * M_PI * fmod((double)(j + 1) * (double)t, f) / f;"),
+    ("angle not reduced", "double ang = 2.0 * M_PI * fmod((double)j * (double)t, f) / f;",
+     "double ang = 2.0 * M_PI * (double)j * (double)t / f;"),
+    ("refinement subtracted", "for (int j = 0; j < p; ++j) beta[j] += dbeta[j];",
+     "for (int j = 0; j < p; ++j) beta[j] -= dbeta[j];"),
     ("reflection not applied to y", "for (int i = j; i < m; ++i) b[i] -= d * A[i * p + j];",
      "for (int i = j; i < m; ++i) b[i] -= 0.5 * d * A[i * p + j];"),
     ("no rank test", "if (norm <= tol) return -1;", "if (norm <= 0.0) return -1;"),

@@ -517,3 +517,73 @@ def test_fill_special_cases(orc):
     ref = orc.fit_monitor(y3[:, None], n=n)
     for k in ref:
         np.testing.assert_array_equal(r[k][..., 3:4], ref[k], err_msg=k)
+
+
+# ------------------------------------------ high signal-to-noise ratio ----
+
+_LD = np.longdouble
+_EXT_CACHE = {}
+
+
+def _extended_reference(Y, N, n, K, f, H):
+    """sigma and MO of Algorithm 1 in x87 extended precision (64-bit mantissa):
+    design rows of Eq. 2 with a long-double pi and sinl/cosl, least squares by
+    classical Gram-Schmidt applied twice, residuals, their scale and brute-force
+    windows.  Independent of the oracle; its own rounding is ~2048 times below
+    FP64's, so it stands for the exact result."""
+    pi = _LD("3.141592653589793238462643383279502884")
+    t = np.arange(1, N + 1).astype(_LD)
+    cols = [np.ones(N, _LD), t / _LD(n)]
+    for j in range(1, K + 1):
+        a = 2 * pi * j * t / _LD(f)
+        cols += [np.sin(a), np.cos(a)]
+    X = np.stack(cols, 1)
+    p = X.shape[1]
+    Q = np.zeros((n, p), _LD)
+    R = np.zeros((p, p), _LD)
+    for j in range(p):
+        v = X[:n, j].copy()
+        for _ in range(2):
+            c = Q[:, :j].T @ v
+            v = v - Q[:, :j] @ c
+            R[:j, j] += c
+        R[j, j] = np.sqrt(v @ v)
+        Q[:, j] = v / R[j, j]
+    Yl = Y.astype(_LD)
+    b = Q.T @ Yl[:n]
+    beta = np.zeros_like(b)
+    for i in range(p - 1, -1, -1):
+        beta[i] = (b[i] - R[i, i + 1:] @ beta[i + 1:]) / R[i, i]
+    r = Yl - X @ beta
+    sig = np.sqrt((r[:n] ** 2).sum(0) / (n - p))
+    C = np.vstack([np.zeros((1, Y.shape[1]), _LD), np.cumsum(r, 0)])
+    tt = np.arange(n + 1, N + 1)
+    mo = (C[tt] - C[tt - H]) / (sig * np.sqrt(_LD(n)))
+    return sig.astype(np.float64), mo.astype(np.float64)
+
+
+@pytest.mark.parametrize("noise,mo_bound", [(1e-5, 2e-10), (1.5e-6, 1e-9)])
+def test_high_snr_matches_extended_precision(orc, noise, mo_bound):
+    """Near the DEGENERATE_SIGMA threshold (sigma <= 1e-6 max|y|) the MOSUM is a
+    small difference of large window sums, so rounding in the design rows or in
+    the fit shows.  Against the extended-precision result: sigma within 1e-10
+    and MO (normwise per pixel) within the bounds here, at noise 1e-5 and 1.5e-6
+    on series of level 0.5-1.2 stored as float32."""
+    if np.finfo(_LD).eps > 1e-18:
+        pytest.skip("long double is not an extended type on this platform")
+    N, n, K, f, H, P = 400, 200, 3, 23.0, 50, 64
+    key = (noise,)
+    if key not in _EXT_CACHE:
+        rng = np.random.default_rng(4)
+        t = np.arange(1, N + 1)[:, None]
+        y = 0.5 + 5e-4 * t + np.zeros((N, P))
+        for j in range(1, K + 1):
+            y += rng.uniform(0, 0.2, P) * np.sin(2 * np.pi * j * t / f + rng.uniform(0, 2 * np.pi, P))
+        y = (y + rng.normal(0, noise, (N, P))).astype(np.float32)
+        _EXT_CACHE[key] = (y,) + _extended_reference(y, N, n, K, f, H)
+    y, sig, mo = _EXT_CACHE[key]
+    r = orc.fit_monitor(y, n=n, order=K, freq=f, h_window=H, lam=2.5)
+    assert (r["status"] == 0).all()
+    assert np.abs(r["sigma"] / sig - 1).max() < 1e-10
+    err = np.abs(r["mosum"] - mo).max(0) / np.abs(mo).max(0)
+    assert err.max() < mo_bound, err.max()
