@@ -16,6 +16,14 @@ constexpr int kMaxOrder = 8;                 // k <= 8, p <= 18
 constexpr int kMaxP = 2 + 2 * kMaxOrder;
 constexpr double kSigmaRelTol = 1e-6;        // DEGENERATE_SIGMA threshold
 constexpr double kRankTol = 1e-6;            // |R_jj| <= tol * sqrt(rows)
+// The history fit's RSS = yy - ||b'||^2 (Gram identity) carries an absolute
+// rounding error of about 1e2 ulp(yy).  A pixel whose RSS falls below
+// kRefineRatio yy (its fit explains all but 1e-4 of yy: a series whose noise is
+// small against its seasonal amplitude and offset) gets its history residuals
+// explicitly instead: its wave streams the history again, forms r_t = d_t -
+// x~_t' beta~, RSS = sum r_t^2, and one step of iterative refinement of beta~.
+// Above the ratio the identity's error stays below 1e-10 of sigma.
+constexpr double kRefineRatio = 1e-4;
 constexpr int kPlainBlock = 64;              // threads per block (one wave), plain path
 // Threads per workgroup of the period-blocked plain kernel: four waves over 256
 // adjacent pixels, so that the row segments they read together are contiguous

@@ -74,6 +74,34 @@ struct Gram {
         }
         return ok;
     }
+
+    // One step of iterative refinement with the factor L of the Gram matrix:
+    // dz = L^-1 dq, beta += L^-T dz where `take` (dq = X~' r, the design's
+    // products with the residuals r at beta).  Returns ||dz||^2, by which the
+    // residual sum of squares at the refined beta falls short of sum r^2.
+    __device__ static double refine(const double* L, const double* dq, double* beta, bool take)
+    {
+        double dz[NP], db[NP];
+        double dd = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            double s = dq[i];
+#pragma unroll
+            for (int k = 0; k < i; ++k) s = fma(-L[tri(i, k)], dz[k], s);
+            dz[i] = s / L[tri(i, i)];
+            dd = fma(dz[i], dz[i], dd);
+        }
+#pragma unroll
+        for (int i = NP - 1; i >= 0; --i) {
+            double s = dz[i];
+#pragma unroll
+            for (int k = i + 1; k < NP; ++k) s = fma(-L[tri(k, i)], db[k], s);
+            db[i] = s / L[tri(i, i)];
+        }
+#pragma unroll
+        for (int i = 0; i < NP; ++i) beta[i] = take ? beta[i] + db[i] : beta[i];
+        return dd;
+    }
 };
 
 }  // namespace dev

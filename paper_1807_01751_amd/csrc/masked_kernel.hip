@@ -121,7 +121,36 @@ __global__ __launch_bounds__(kMaskedBlock) void masked_kernel(MaskedArgs a)
         for (int k = i + 1; k < NP; ++k) s = fma(-L[tri(k, i)], beta[k], s);
         beta[i] = s / L[tri(i, i)];
     }
-    const double sig = sqrt(fmax(yy - zz, 0.0) / (double)(nv - NP));
+    // High signal-to-noise: RSS = yy - ||z||^2 cancels (see kRefineRatio).  The
+    // lanes concerned get explicit residuals of their observed history rows from
+    // a second pass (wave-uniform), RSS = sum r_t^2 - ||L^-1 X~' r||^2 and one
+    // refinement step beta~ += L^-T L^-1 X~' r.
+    double rss = yy - zz;
+    const bool refine = fitted && rss < kRefineRatio * yy;
+    if (__ballot(refine) != 0) {
+        double dq[NP], rr = 0.0;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) dq[j] = 0.0;
+        auto row2 = [&](int t, float v, bool used) {
+            if (used) {
+                const ctab xr = x + t * NP;
+                double r = (double)v - c;
+#pragma unroll
+                for (int j = 0; j < NP; ++j) r = fma(-xr[j], beta[j], r);
+                rr = fma(r, r, rr);
+#pragma unroll
+                for (int j = 0; j < NP; ++j) dq[j] = fma(xr[j], r, dq[j]);
+            }
+        };
+        if (EXPLICIT)
+            stream_rows<kMU>(FlaggedCursor{Y, a.valid, ld, a.ldv, lane}, 0, n,
+                             [&](int t, FlaggedObs o) { row2(t, o.y, o.ok != 0); });
+        else
+            stream_rows<kMU>(ObsCursor{Y, ld, lane * 4u}, 0, n,
+                             [&](int t, float v) { row2(t, v, isfinite(v)); });
+        rss = refine ? rr - Gk::refine(L, dq, beta, refine) : rss;
+    }
+    const double sig = sqrt(fmax(rss, 0.0) / (double)(nv - NP));
     const double scale = sig * sqrt((double)nv);
     if (st == BFM_ST_OK && sig <= kSigmaRelTol * (double)ymax) st = BFM_ST_DEGENERATE_SIGMA;
 

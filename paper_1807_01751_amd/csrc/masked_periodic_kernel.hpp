@@ -379,7 +379,42 @@ masked_periodic_kernel(MaskedArgs a)
         for (int k = i + 1; k < NP; ++k) s = fma(-L[tri(k, i)], beta[k], s);
         beta[i] = s / L[tri(i, i)];
     }
-    const double sig = sqrt(fmax(yy - zz, 0.0) / (double)(nv - NP));
+    // High signal-to-noise: RSS = yy - ||z||^2 cancels (see kRefineRatio).  The
+    // lanes concerned get explicit residuals of their observed history rows from
+    // a second pass (wave-uniform), r_t = (y_t - c) - x~_t' beta~, RSS = sum r_t^2
+    // - ||L^-1 X~' r||^2 and one refinement step beta~ += L^-T L^-1 X~' r.
+    double rss = yy - zz;
+    const bool refine = fitted && rss < kRefineRatio * yy;
+    if (__ballot(refine) != 0) {
+        double dq[NP], rr = 0.0;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) dq[j] = 0.0;
+        stream_blocks<F>(
+            [&](int t) { return Cur::at(a, t, lane); }, 0, n,
+            [&](int u, int t, V val, bool in) {
+                if (in && observed(val)) {
+                    const double tau = ((double)t - c0) * inv_n;
+                    double f = fma(beta[1], tau, beta[0]);
+#pragma unroll
+                    for (int j = 1; j <= K; ++j) {
+                        f = fma(beta[2 * j], ph[u * NT + 2 * (j - 1)], f);
+                        f = fma(beta[2 * j + 1], ph[u * NT + 2 * (j - 1) + 1], f);
+                    }
+                    const double r = ((double)value(val) - c) - f;
+                    rr = fma(r, r, rr);
+                    dq[0] += r;
+                    dq[1] = fma(tau, r, dq[1]);
+#pragma unroll
+                    for (int j = 1; j <= K; ++j) {
+                        dq[2 * j] = fma(ph[u * NT + 2 * (j - 1)], r, dq[2 * j]);
+                        dq[2 * j + 1] = fma(ph[u * NT + 2 * (j - 1) + 1], r, dq[2 * j + 1]);
+                    }
+                }
+            },
+            [](int) {}, [](const V*) {});
+        rss = refine ? rr - Gk::refine(L, dq, beta, refine) : rss;
+    }
+    const double sig = sqrt(fmax(rss, 0.0) / (double)(nv - NP));
     const double scale = sig * sqrt((double)nv);
     if (st == BFM_ST_OK && sig <= kSigmaRelTol * (double)__uint_as_float(ymaxb))
         st = BFM_ST_DEGENERATE_SIGMA;

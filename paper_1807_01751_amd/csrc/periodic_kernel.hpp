@@ -7,7 +7,9 @@
 //            Afterwards g = X~_n' d follows from the F phase sums (harmonics
 //            at each phase from a small table) and Tr (trend), b' = R^-T g
 //            (coordinates in the orthonormal basis of Section 3's shared
-//            operator), RSS = yy - ||b'||^2, beta~ = R^-1 b'.
+//            operator), RSS = yy - ||b'||^2, beta~ = R^-1 b'.  Where that
+//            identity cancels (RSS < kRefineRatio yy) the wave streams its
+//            history again for explicit residuals and one refinement step.
 //   monitor  the window sum of fitted values (Eq. 3) is
 //            Lc + gamma (t+1) + Pw[t mod F]: a linear trend part and a per-phase
 //            part, both computed once per pixel.  S'_t = S'_{t-1} + y_t -
@@ -36,6 +38,64 @@ namespace bfm {
 namespace {
 
 using namespace dev;
+
+// Residual sums over history rows [t0, t1) at the fitted coefficients beta~
+// (centred-trend basis of the centred series, tau_t = (t + 1 - (n+1)/2) / n):
+// r_t = (y_t - c) - x~_t' beta~, rr += r_t^2, dg += x~_t r_t.  Rows are
+// streamed in blocks aligned to multiples of F like the first pass.
+template <int K, int F, typename Cursor, typename Obs>
+__device__ __forceinline__ void history_residual_sums(Cursor cur, int t0, int t1, int n, double c,
+                                                      Obs&& obs, ctab hh, const double* beta,
+                                                      double* dg, double& rr)
+{
+    constexpr int NH = 2 * K;
+    const double tc = 0.5 * (double)(n + 1);
+    const double inv_n = 1.0 / (double)n;
+    stream_aligned<F>(
+        cur, t0, t1,
+        [&](int u, int t, float v) {
+            v = obs(v);
+            const double tau = ((double)(t + 1) - tc) * inv_n;
+            double f = fma(beta[1], tau, beta[0]);
+#pragma unroll
+            for (int j = 0; j < NH; ++j) f = fma(hh[u * NH + j], beta[2 + j], f);
+            const double r = ((double)v - c) - f;
+            rr = fma(r, r, rr);
+            dg[0] += r;
+            dg[1] = fma(tau, r, dg[1]);
+#pragma unroll
+            for (int j = 0; j < NH; ++j) dg[2 + j] = fma(hh[u * NH + j], r, dg[2 + j]);
+        },
+        [](int, int, int) {});
+}
+
+// One step of iterative refinement from the residual sums of the history:
+// beta~ += R^-1 R^-T dg, and RSS = rr - ||R^-T dg||^2, the residual sum of
+// squares at the refined coefficients (the correction is orthogonal to the new
+// residuals).  Only lanes with `take` change.
+template <int NP>
+__device__ __forceinline__ void refine_apply(ctab rt, ctab ri, const double* dg, double rr, bool take,
+                                             double* beta, double& rss)
+{
+    double db[NP];
+    double dd = 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k <= i; ++k) s = fma(rt[i * NP + k], dg[k], s);
+        db[i] = s;
+        dd = fma(s, s, dd);
+    }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = i; k < NP; ++k) s = fma(ri[i * NP + k], db[k], s);
+        beta[i] = take ? beta[i] + s : beta[i];
+    }
+    rss = take ? rr - dd : rss;
+}
 
 template <int K, int F, bool EXPORT, typename T, bool FILL>
 #ifndef BFM_PERIODIC_OCC
@@ -140,9 +200,21 @@ void periodic_kernel(PeriodicArgs a)
         for (int k = i; k < NP; ++k) s = fma(ri[i * NP + k], bq[k], s);
         beta[i] = s;
     }
+    const double tc = 0.5 * (double)(n + 1);
+    // High signal-to-noise: explicit history residuals and one refinement step
+    // for the lanes whose RSS the Gram identity cannot resolve (wave-uniform).
+    const bool refine = rss < kRefineRatio * yy;
+    if (__ballot(refine) != 0) {
+        double dg[NP], rr = 0.0;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) dg[j] = 0.0;
+        Filler fill2{c0};
+        history_residual_sums<K, F>(BlockCursorT<T>(Y, ld, lane), 0, n, n, c,
+                                    [&](float v) { return FILL ? fill2(v) : v; }, hh, beta, dg, rr);
+        refine_apply<NP>(rt, ri, dg, rr, refine, beta, rss);
+    }
     const double sig = sqrt(fmax(rss, 0.0) * a.inv_dof);
     const double scale = sig * a.sqrt_n;
-    const double tc = 0.5 * (double)(n + 1);
     const double qnan = __builtin_nan("");
     const bool hist_bad = !isfinite(yy);
     const bool degenerate = sig <= kSigmaRelTol * (double)__uint_as_float(ymax_bits);
@@ -278,7 +350,8 @@ void periodic_kernel(PeriodicArgs a)
 // them), runs the same per-row recursion, and the first crossing, max and min
 // are combined over the waves at the end.
 //
-// LDS (bytes): max(NS (F + 3) 512, (F + NP + 5) 512 + NS H 256).
+// LDS (bytes): max(NS (F + 3) 512, (F + NP + 5) 512 + NS H 256,
+// (F + NP + 5 + (NS + 1)(NP + 1)) 512).
 template <int K, int F, int NS, bool EXPORT, typename T>
 __global__ __launch_bounds__(kPlainBlock * NS) void periodic_split_kernel(PeriodicArgs a)
 {
@@ -302,6 +375,8 @@ __global__ __launch_bounds__(kPlainBlock * NS) void periodic_split_kernel(Period
     const ctab bnd = wh + F * NH;
     double* const part = lds + tid;               // [NS][F + 3][64]
     double* const bc = lds + tid;                  // [NB][64] after the combine
+    // refinement: beta and flag [NP + 1][64], then [NS][NP + 1][64] partial sums
+    double* const rf = lds + NB * kPlainBlock + tid;
     float* const myring = reinterpret_cast<float*>(lds + NB * kPlainBlock) + w * H * kPlainBlock + tid;
 
     // ---- this wave's share of the history blocks ----
@@ -336,6 +411,7 @@ __global__ __launch_bounds__(kPlainBlock * NS) void periodic_split_kernel(Period
     const double qnan = __builtin_nan("");
     bool hist_bad = false, degenerate = false;
     double beta[NP];
+    double rss = 0.0;
     if (w == 0) {
         // ---- sum of the shares (in wave order) and the fit ----
         for (int v = 1; v < NS; ++v) {
@@ -363,7 +439,7 @@ __global__ __launch_bounds__(kPlainBlock * NS) void periodic_split_kernel(Period
             g[2 + j] = sj;
         }
         double bq[NP];
-        double rss = yy;
+        rss = yy;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
             double sv = 0.0;
@@ -379,6 +455,45 @@ __global__ __launch_bounds__(kPlainBlock * NS) void periodic_split_kernel(Period
             for (int k = i; k < NP; ++k) sv = fma(ri[i * NP + k], bq[k], sv);
             beta[i] = sv;
         }
+        // the coefficients and the refinement flag, for every wave (past the
+        // broadcast rows, which wave 0 writes below while the others may still
+        // read these)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) rf[j * kPlainBlock] = beta[j];
+        rf[NP * kPlainBlock] = rss < kRefineRatio * yy ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // High signal-to-noise (the same 64 flags in every wave): each wave sums the
+    // residuals of its history share, wave 0 adds the shares in wave order and
+    // refines the lanes whose RSS the Gram identity cannot resolve.
+    const bool refine = rf[NP * kPlainBlock] != 0.0;
+    if (__ballot(refine) != 0) {
+        double dg[NP], rr = 0.0, bt[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            dg[j] = 0.0;
+            bt[j] = rf[j * kPlainBlock];
+        }
+        if (h0 < h1)
+            history_residual_sums<K, F>(BlockCursorT<T>(Y + (int64_t)h0 * ld, ld, lane), h0, h1, n, c,
+                                        [](float v) { return v; }, hh, bt, dg, rr);
+        double* const rp = rf + (size_t)(1 + w) * (NP + 1) * kPlainBlock;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) rp[j * kPlainBlock] = dg[j];
+        rp[NP * kPlainBlock] = rr;
+        __syncthreads();
+        if (w == 0) {
+            for (int v = 1; v < NS; ++v) {
+                const double* q = rf + (size_t)(1 + v) * (NP + 1) * kPlainBlock;
+#pragma unroll
+                for (int j = 0; j < NP; ++j) dg[j] += q[j * kPlainBlock];
+                rr += q[NP * kPlainBlock];
+            }
+            refine_apply<NP>(rt, ri, dg, rr, refine, beta, rss);
+        }
+        __syncthreads();  // the refinement area is free again
+    }
+    if (w == 0) {
         const double sig = sqrt(fmax(rss, 0.0) * a.inv_dof);
         hist_bad = !isfinite(yy);
         degenerate = sig <= kSigmaRelTol * (double)__uint_as_float(ymax_bits);
@@ -530,9 +645,11 @@ __global__ __launch_bounds__(kPlainBlock * NS) void periodic_split_kernel(Period
 __host__ __device__ constexpr size_t split_lds_bytes(int F, int NP, int NS, int H)
 {
     const size_t partials = (size_t)NS * (F + 3) * kPlainBlock * 8;
+    const size_t refine = ((size_t)(F + NP + 5) + (size_t)(NS + 1) * (NP + 1)) * kPlainBlock * 8;
     const size_t monitor = (size_t)(F + NP + 5) * kPlainBlock * 8 + (size_t)NS * H * kPlainBlock * 4;
     const size_t combine = (size_t)3 * NS * kPlainBlock * 8;
     size_t m = partials > monitor ? partials : monitor;
+    m = m > refine ? m : refine;
     return m > combine ? m : combine;
 }
 

@@ -10,6 +10,8 @@
 //       b' += q_t (y_t - c)      coordinates in the orthonormal history basis
 //       yy += (y_t - c)^2        so that RSS = yy - ||b'||^2
 //     c = y_0 centres the series; the intercept absorbs it exactly.
+//     Where RSS < kRefineRatio yy (the identity cancels) the wave streams its
+//     history again for explicit residuals and one refinement step.
 //   monitoring rows t >= n (Eq. 3, Algorithm 1 steps 6-13)
 //       S_t = S_{t-1} + y_t - y_{t-H}   window sum of the observations; the
 //             value H rows back comes from a per-lane ring in LDS
@@ -103,6 +105,34 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
     double rss = yy;
 #pragma unroll
     for (int j = 0; j < NP; ++j) rss = fma(-bq[j], bq[j], rss);
+    // High signal-to-noise: the identity cancels (see kRefineRatio).  The lanes
+    // concerned get explicit history residuals r_t = d_t - q_t' b' from a second
+    // pass over the history (wave-uniform), RSS = sum r_t^2 - ||Q' r||^2 and one
+    // refinement step b' += Q' r (Q has orthonormal columns).
+    const bool refine = rss < kRefineRatio * yy;
+    if (__ballot(refine) != 0) {
+        double db[NP], rr = 0.0;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) db[j] = 0.0;
+        Filler fill2{c0};
+        stream_rows<kU>(ObsCursor{Y, ld, lane_bytes}, 0, n, [&](int t, float v) {
+            if (FILL) v = fill2(v);
+            const ctab qt = q + t * NP;
+            double r = (double)v - c;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) r = fma(-qt[j], bq[j], r);
+            rr = fma(r, r, rr);
+#pragma unroll
+            for (int j = 0; j < NP; ++j) db[j] = fma(qt[j], r, db[j]);
+        });
+        double dd = 0.0;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            dd = fma(db[j], db[j], dd);
+            bq[j] = refine ? bq[j] + db[j] : bq[j];
+        }
+        rss = refine ? rr - dd : rss;
+    }
     const double sig = sqrt(fmax(rss, 0.0) * a.inv_dof);
     const double scale = sig * a.sqrt_n;
     const double qnan = __builtin_nan("");
