@@ -272,6 +272,26 @@ int bfm_critical_value(bfm_ctx *ctx, const bfm_params *prm, double alpha, int64_
                        uint64_t seed, double *lambda, void *stream);
 
 /*
+ * bfm_critical_value for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, result and errors as bfm_critical_value (the same kernels; the
+ * value equals its for the same seed and paths), but the simulated statistics
+ * and the selection's counters live in a fixed device array of the library
+ * (BFM_NOALLOC_MAX_PATHS * 8 + 1024 bytes, one per GPU, held from the first
+ * bfm_create on that GPU until the process ends) instead of memory allocated
+ * for the call: no hipMalloc, hipFree or other allocating call is made.
+ * paths must be in [1, BFM_NOALLOC_MAX_PATHS] (BFM_E_INVAL otherwise).  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (from
+ * several host threads or streams) race and must be serialised by the caller.
+ * The counters are cleared by a kernel at the start of each selection pass;
+ * the statistics of paths 0 .. paths-1 are written before they are read.
+ * Synchronises `stream` before returning.
+ */
+#define BFM_NOALLOC_MAX_PATHS 4194304
+int bfm_critical_value_noalloc(bfm_ctx *ctx, const bfm_params *prm, double alpha, int64_t paths,
+                               uint64_t seed, double *lambda, void *stream);
+
+/*
  * Serving.  A server runs requests of different sizes and parameters as they
  * arrive, several at a time: each admitted request runs on one of `slots` HIP
  * streams of the server's device (non-blocking, default priority), so the work

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_PKG, "libbfm.so")
 SUCCESS = 0
 E_INVAL, E_LAYOUT, E_NOMEM, E_NODEVICE, E_HIP, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
 MASK_NONE, MASK_NAN, MASK_EXPLICIT, MASK_FILL = 0, 1, 2, 3
+NOALLOC_MAX_PATHS = 4194304  # BFM_NOALLOC_MAX_PATHS
 PREC_FP64 = 0
 Y_F32, Y_BF16, Y_F16 = 0, 1, 2
 _Y_DTYPES = {torch.float32: Y_F32, torch.bfloat16: Y_BF16, torch.float16: Y_F16}
@@ -36,7 +37,7 @@ EXPORTS = ("bfm_version", "bfm_last_error", "bfm_check_params", "bfm_create", "b
            "bfm_fit_monitor", "bfm_fit_monitor_typed", "bfm_host_operators", "bfm_request_bytes",
            "bfm_server_create", "bfm_server_submit", "bfm_server_wait", "bfm_server_release",
            "bfm_server_take", "bfm_autotune", "bfm_tune_set", "bfm_mosum_null_sup",
-           "bfm_critical_value", "bfm_workspace_bytes",
+           "bfm_critical_value", "bfm_critical_value_noalloc", "bfm_workspace_bytes",
            "bfm_server_get_stats", "bfm_server_destroy")
 WANT = {"mag": 1, "sigma": 2, "status": 4, "beta": 8, "resid": 16, "mosum": 32}
 
@@ -136,6 +137,7 @@ def load():
     lib.bfm_workspace_bytes.argtypes = [P_, i64, ctypes.POINTER(ctypes.c_size_t)]
     lib.bfm_critical_value.argtypes = [vp, P_, ctypes.c_double, i64, ctypes.c_uint64,
                                        ctypes.POINTER(ctypes.c_double), vp]
+    lib.bfm_critical_value_noalloc.argtypes = lib.bfm_critical_value.argtypes
     R_ = ctypes.POINTER(Request)
     lib.bfm_request_bytes.argtypes = [R_, ctypes.POINTER(ctypes.c_size_t)]
     lib.bfm_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_size_t]
@@ -309,6 +311,21 @@ def critical_value(alpha: float, *, n: int, N: int, h: float = 0.25, h_window: i
     _raise(load().bfm_critical_value(context(device), ctypes.byref(prm), ctypes.c_double(alpha),
                                      int(paths), ctypes.c_uint64(seed), ctypes.byref(out),
                                      s.cuda_stream))
+    return out.value
+
+
+def critical_value_noalloc(alpha: float, *, n: int, N: int, h: float = 0.25, h_window: int = 0,
+                           paths: int = 100000, seed: int = 0, device: int = 0,
+                           stream: torch.cuda.Stream | None = None) -> float:
+    """bfm_critical_value_noalloc: the same value as critical_value, computed in
+    the library's fixed scratch array (no device allocation; paths <=
+    NOALLOC_MAX_PATHS; calls that overlap on one GPU race)."""
+    prm = make_params(N, n, 0, 23.0, h, h_window, 1.0, MASK_NONE)
+    out = ctypes.c_double()
+    s = stream if stream is not None else torch.cuda.current_stream(torch.device(f"cuda:{device}"))
+    _raise(load().bfm_critical_value_noalloc(context(device), ctypes.byref(prm), ctypes.c_double(alpha),
+                                             int(paths), ctypes.c_uint64(seed), ctypes.byref(out),
+                                             s.cuda_stream))
     return out.value
 
 

@@ -318,6 +318,12 @@ int bfm_create(bfm_ctx** out, int device)
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(BFM_E_UNSUPPORTED, "device %d is %s; libbfm is built for gfx950", device,
                     prop.gcnArchName);
+    {
+        // The device address of the no-allocation scratch array, once per device.
+        DeviceGuard g(device);
+        if ((e = bfm::noalloc_scratch_init(device)) != hipSuccess)
+            return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    }
     bfm_ctx* ctx = new (std::nothrow) bfm_ctx;
     if (!ctx) return fail(BFM_E_NOMEM, "context allocation failed");
     ctx->device = device;
@@ -574,31 +580,72 @@ int bfm_mosum_null_sup(bfm_ctx* ctx, const bfm_params* prm, uint64_t seed, int64
     return e == hipSuccess ? BFM_SUCCESS : hip_fail(e, "null MOSUM kernel launch");
 }
 
+namespace {
+
+// Checks of both critical-value entry points; *H the window, *rank the order
+// statistic.
+int critical_args(bfm_ctx* ctx, const bfm_params* prm, double alpha, int64_t paths, int64_t max_paths,
+                  const double* lambda, int* H, int64_t* rank)
+{
+    int rc = null_shape(ctx, prm, H);
+    if (rc) return rc;
+    if (!(alpha > 0 && alpha < 1)) return fail(BFM_E_INVAL, "alpha must be in (0, 1)");
+    if (paths < 1 || paths > max_paths)
+        return fail(BFM_E_INVAL, "paths must be in [1, %lld] (got %lld)", (long long)max_paths,
+                    (long long)paths);
+    if (!lambda) return fail(BFM_E_INVAL, "lambda is NULL");
+    *rank = (int64_t)std::ceil((1.0 - alpha) * (double)paths - 1e-9);
+    *rank = std::max<int64_t>(1, std::min(*rank, paths));
+    return BFM_SUCCESS;
+}
+
+// Simulation and selection over `sup` (paths doubles) and `counts` (256 uint32).
+hipError_t critical_on(const bfm_params* prm, int H, int64_t paths, uint64_t seed, int64_t rank,
+                       double* sup, uint32_t* counts, double* lambda, hipStream_t s)
+{
+    hipError_t e = bfm::launch_mosum_null_sup(prm->n_hist, prm->n_obs, H, seed, 0, paths, sup, s);
+    if (e == hipSuccess) e = bfm::select_rank(sup, paths, rank, counts, lambda, s);
+    return e;
+}
+
+}  // namespace
+
 int bfm_critical_value(bfm_ctx* ctx, const bfm_params* prm, double alpha, int64_t paths, uint64_t seed,
                        double* lambda, void* stream)
 {
     int H = 0;
-    int rc = null_shape(ctx, prm, &H);
+    int64_t rank = 0;
+    int rc = critical_args(ctx, prm, alpha, paths, (int64_t)1 << 31, lambda, &H, &rank);
     if (rc) return rc;
-    if (!(alpha > 0 && alpha < 1)) return fail(BFM_E_INVAL, "alpha must be in (0, 1)");
-    if (paths < 1 || paths > ((int64_t)1 << 31)) return fail(BFM_E_INVAL, "paths must be in [1, 2^31]");
-    if (!lambda) return fail(BFM_E_INVAL, "lambda is NULL");
-    int64_t rank = (int64_t)std::ceil((1.0 - alpha) * (double)paths - 1e-9);
-    rank = std::max<int64_t>(1, std::min(rank, paths));
     DeviceGuard g(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     void* buf = nullptr;
     hipError_t e = hipMalloc(&buf, (size_t)paths * sizeof(double) + 256 * sizeof(uint32_t));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(null paths)");
     double* sup = static_cast<double*>(buf);
-    uint32_t* counts = reinterpret_cast<uint32_t*>(sup + paths);
-    e = bfm::launch_mosum_null_sup(prm->n_hist, prm->n_obs, H, seed, 0, paths, sup, s);
-    if (e == hipSuccess) e = bfm::select_rank(sup, paths, rank, counts, lambda, s);
+    e = critical_on(prm, H, paths, seed, rank, sup, reinterpret_cast<uint32_t*>(sup + paths), lambda, s);
     // select_rank has synchronised the stream; the buffer is idle.
     hipError_t ef = hipFree(buf);
     if (e != hipSuccess) return hip_fail(e, "critical value");
     if (ef != hipSuccess) return hip_fail(ef, "hipFree(null paths)");
     return BFM_SUCCESS;
+}
+
+int bfm_critical_value_noalloc(bfm_ctx* ctx, const bfm_params* prm, double alpha, int64_t paths,
+                               uint64_t seed, double* lambda, void* stream)
+{
+    int H = 0;
+    int64_t rank = 0;
+    int rc = critical_args(ctx, prm, alpha, paths, BFM_NOALLOC_MAX_PATHS, lambda, &H, &rank);
+    if (rc) return rc;
+    void* buf = bfm::noalloc_scratch(ctx->device);  // looked up by bfm_create
+    if (!buf) return fail(BFM_E_HIP, "no scratch address for device %d", ctx->device);
+    DeviceGuard g(ctx->device);
+    double* sup = static_cast<double*>(buf);
+    uint32_t* counts = reinterpret_cast<uint32_t*>(static_cast<unsigned char*>(buf) +
+                                                   (size_t)BFM_NOALLOC_MAX_PATHS * sizeof(double));
+    hipError_t e = critical_on(prm, H, paths, seed, rank, sup, counts, lambda, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? BFM_SUCCESS : hip_fail(e, "critical value (no allocation)");
 }
 
 int bfm_tune_set(bfm_ctx* ctx, const bfm_params* prm, int32_t y_dtype, int64_t P, int32_t split)

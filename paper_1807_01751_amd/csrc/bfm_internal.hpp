@@ -194,6 +194,12 @@ hipError_t launch_mosum_null_sup(int n, int N, int H, uint64_t seed, int64_t pat
                                  double* sup, hipStream_t stream);
 hipError_t select_rank(const double* v, int64_t cnt, int64_t rank, uint32_t* counts, double* out,
                        hipStream_t stream);
+// The fixed scratch array of bfm_critical_value_noalloc (BFM_NOALLOC_MAX_PATHS
+// doubles, then 256 uint32 counters): noalloc_scratch_init looks up its device
+// address on `device` (which must be current) once and keeps it;
+// noalloc_scratch returns the kept address (nullptr before the lookup).
+hipError_t noalloc_scratch_init(int device);
+void* noalloc_scratch(int device);
 
 // Every pixel gets `st` (or NONFINITE if one of its used observations is not
 // finite), brk = -1 and NaN floating outputs: used when the parameters make

@@ -24,8 +24,16 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "bfm_internal.hpp"
+
+// Scratch of bfm_critical_value_noalloc: the statistics of up to
+// BFM_NOALLOC_MAX_PATHS paths, then the 256 digit counters of the selection.
+// Each GPU holds its own copy at its own address; host code reaches it only
+// through the address noalloc_scratch_init looked up (the array's name is a
+// host-side stand-in, not a device address).
+static __device__ __align__(256) unsigned char scratch[(size_t)BFM_NOALLOC_MAX_PATHS * 8 + 1024];
 
 namespace bfm {
 namespace {
@@ -130,7 +138,30 @@ __global__ __launch_bounds__(kLamBlock) void select_digit_kernel(const uint64_t*
 
 __global__ void zero_counts_kernel(uint32_t* counts) { counts[threadIdx.x] = 0; }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices];  // device address of `scratch`, per device
+
 }  // namespace
+
+hipError_t noalloc_scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[device] = p;
+    return hipSuccess;
+}
+
+void* noalloc_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch[device];
+}
 
 hipError_t launch_mosum_null_sup(int n, int N, int H, uint64_t seed, int64_t path0, int64_t paths,
                                  double* sup, hipStream_t stream)
