@@ -26,6 +26,15 @@ unevenly spaced acquisitions, day numbers with f = 365, n = 144, h = 72) on
 the table-driven kernel (times), and the simulated critical value from one
 million no-change paths (lambda).
 
+Two more legs follow: the small tile of the first configuration (64 x 64
+pixels, N = 228) timed call by call, warm and with the L2 caches and the MALL
+flushed before each call ("latency_tile"), and the largest tile (4096 x 4096
+pixels, N = 512, 10% NaN, p = 8 and 10, float32 and FP16 storage) on the
+missing-value kernel ("config4").  In the CPU-baseline leg the oracle also
+checks sampled pixels of every leg against the GPU's FP64 outputs of the same
+kernels ("accuracy": sigma, magnitude and MOSUM errors, break agreement,
+marginal and non-marginal break mismatches).
+
 Prints one JSON line.  Run with --gpus 1 (the default); more GPUs are not
 supported by this benchmark.
 """
@@ -72,11 +81,24 @@ LEGS = {
               "workload": "2400x1851 pixels, N=288 acquisition days, f=365",
               "pixels": 2400 * 1851, "n_obs": 288},
 }
+for _k, _ord in (("k8", 3), ("k10", 4)):
+    for _st, _yb in (("f32", 4), ("f16", 2)):
+        _T = "float" if _st == "f32" else "bfm::dev::f16_t"
+        LEGS[f"config4_{_k}_{_st}"] = {
+            "kernel": f"::masked_periodic_kernel<{_ord}, 23, false, false, {_T}>(",
+            "traffic": os.path.join(PROFILES, f"traffic_config4_{_k}_{_st}_4096x4096_N512_nan10.json"),
+            "trace_md": os.path.join(PROFILES, f"config4_masked_periodic_{_k}_{_st}_4096x4096_N512_nan10"
+                                                "_kernel_trace.md"),
+            "workload": f"4096x4096 pixels, N=512, 10% NaN, p={2 + 2 * _ord}, {_st} storage",
+            "pixels": 1 << 24, "n_obs": 512, "y_bytes": _yb,
+            # 5 timed and 5 latency-pass launches, then the untimed FP64 sample call
+            "launches": 10, "skip_last": 1}
 CHILE_P, CHILE_N, CHILE_n, CHILE_H = 2400 * 1851, 288, 144, 72
 FILL_MISSING = 0.10
 LAMBDA_PATHS = 1 << 20
+ACC_STRIDE = 128  # every 128th pixel of a 1024x1024 tile is checked against the oracle
 PROFILE_CMD = ("rocprofv3 {flags} -f csv -d <dir> -o run -- python3 bench.py --steps 10 "
-               "--warmup 2 --no-cpu-baseline --copy-calibration")
+               "--warmup 2 --no-cpu-baseline --no-serving --copy-calibration")
 PROFILED_LAUNCHES = 20  # the --steps 10 timed launches of PROFILE_CMD and the 10 of the latency pass
 
 
@@ -132,15 +154,103 @@ def cpu_baseline(Y, seconds):
                       f"{dt:.1f} s on {threads} host threads"}
 
 
+# Sampled pixels of each leg, checked against the oracle in the CPU-baseline leg:
+# the leg's tile (or a sample of its columns), the GPU's FP64 outputs for those
+# pixels from the same kernels the leg times, and the oracle's arguments.
+SAMPLES = []
+
+
+def gpu_sample(leg, bfm, Y, idx, *, n_hist, lam, mask_mode=0, mosum=True, ref=None, **kw):
+    """Run the leg's call once more (untimed) with FP64 outputs and keep the
+    sampled pixels.  The lean and exporting kernels compute identically, so a
+    MOSUM export does not change what is compared.  `ref` names another
+    sample's GPU result to compare break indices with (storage agreement)."""
+    import torch
+    outs = ("brk", "mag", "sigma", "status") + (("mosum",) if mosum else ())
+    g = bfm.fit_monitor(Y, n=n_hist, lam=lam, mask_mode=mask_mode, outputs=outs,
+                        out_dtype=torch.float64, **kw)
+    sel = torch.as_tensor(idx, device=Y.device)
+    g = {k: (v[:, sel] if v.dim() == 2 else v[sel]).cpu().numpy() for k, v in g.items()}
+    SAMPLES.append({"leg": leg, "Y": Y[:, sel].float().cpu().numpy(), "g": g, "n": n_hist,
+                    "lam": lam, "mask_mode": mask_mode, "kw": kw, "ref": ref})
+
+
+def accuracy(s, o):
+    """FP64-oracle error of one sample (the parity rule of the tests): relative
+    error of sigma and the magnitude, normwise MOSUM error per pixel, break
+    agreement, and mismatched break indices split into marginal ones (the
+    oracle's MOSUM within 1e-8, relative, of the boundary at a position up to
+    the later break) and the rest."""
+    import numpy as np
+    g, n, lam = s["g"], s["n"], s["lam"]
+    ok = (o["status"] == 0) & (g["status"] == 0)
+    rep = {"pixels": int(ok.size), "status_agreement": float((g["status"] == o["status"]).mean()),
+           "not_ok": int((o["status"] != 0).sum())}
+    for k in ("sigma", "mag"):
+        e = np.abs(g[k][ok] - o[k][ok]) / np.maximum(np.abs(o[k][ok]), 1e-300)
+        rep[f"max_rel_{k}"] = float(e.max()) if e.size else 0.0
+        rep[f"p999_rel_{k}"] = float(np.quantile(e, 0.999)) if e.size else 0.0
+    mo = o["mosum"]
+    if "mosum" in g:
+        a, b = g["mosum"][:, ok], mo[:, ok]
+        e = np.nanmax(np.abs(a - b), axis=0) / np.maximum(np.nanmax(np.abs(b), axis=0), 1e-300)
+        rep["max_rel_mosum"] = float(e.max()) if e.size else 0.0
+        rep["p999_rel_mosum"] = float(np.quantile(e, 0.999)) if e.size else 0.0
+    M = mo.shape[0]
+    fin = np.isfinite(mo)
+    if s["mask_mode"] == 1:  # compacted positions u / n_v
+        nv = np.isfinite(s["Y"][:n]).sum(0).astype(np.float64)
+        x = (nv[None, :] + np.cumsum(fin, axis=0)) / nv[None, :]
+    else:
+        x = np.broadcast_to(((n + 1 + np.arange(M)) / n)[:, None], mo.shape)
+    bnd = lam * np.sqrt(np.where(x <= np.e, 1.0, np.log(np.maximum(x, 1.0))))
+    with np.errstate(invalid="ignore"):
+        rel = np.abs(np.abs(mo) - bnd) / bnd
+    last = np.maximum(g["brk"], o["brk"])
+    last = np.where(last < 0, M - 1, last)
+    rel = np.where((np.arange(M)[:, None] <= last[None, :]) & fin, rel, np.inf)
+    margin = rel.min(axis=0)
+    diff = g["brk"] != o["brk"]
+    rep["brk_agreement"] = float(1.0 - diff.mean())
+    rep["brk_mismatch_marginal"] = int((diff & (margin < 1e-8)).sum())
+    rep["brk_mismatch_not_marginal"] = int((diff & ~(margin < 1e-8)).sum())
+    return rep
+
+
+def check_samples(threads):
+    """The oracle on every leg's sample: accuracy per leg (the oracle runs here
+    only, in the CPU-baseline leg)."""
+    import numpy as np
+
+    from oracle import oracle
+    res, by_leg = {}, {}
+    t0 = time.perf_counter()
+    for s in SAMPLES:
+        kw = {k: v for k, v in s["kw"].items() if k in ("order", "freq", "h", "h_window", "times")}
+        o = oracle.fit_monitor(s["Y"], n=s["n"], lam=s["lam"], mask_mode=s["mask_mode"], threads=threads,
+                               **kw)
+        rep = accuracy(s, o)
+        if s["ref"] is not None:  # break agreement with the float32 series' GPU result
+            rep[f"brk_agreement_with_{s['ref']}"] = float((s["g"]["brk"] == by_leg[s["ref"]]["brk"]).mean())
+            oref = by_leg[s["ref"] + "/oracle"]
+            rep[f"brk_agreement_with_{s['ref']}_oracle"] = float((s["g"]["brk"] == oref["brk"]).mean())
+        by_leg[s["leg"]], by_leg[s["leg"] + "/oracle"] = s["g"], o
+        res[s["leg"]] = rep
+    log(f"bench: oracle check of {len(SAMPLES)} samples in {time.perf_counter() - t0:.1f} s")
+    return res
+
+
 def _csv(path):
     import csv
     with open(path) as f:
         return list(csv.DictReader(f))
 
 
-def summarize_profiles(d):
+def summarize_profiles(d, bench_line=None):
     """Turn rocprofv3 CSV output of the three passes under ``d`` (trace/, fetch/,
-    write/) into the summaries kept in profiles/, one set per leg."""
+    write/) into the summaries kept in profiles/, one set per leg.  With
+    ``bench_line`` (the JSON line of a plain bench.py run in the same job), each
+    summary also records that line's step time and the leg's HIP-event mean."""
     import glob
     import re
     P_ALG = (4 * N + 8) * P
@@ -163,8 +273,10 @@ def summarize_profiles(d):
         # warmup and timed steps; the untimed pre-warm of the plain leg comes
         # before them).
         grid = (pixels + 63) // 64 * 64
+        take, skip = spec.get("launches", PROFILED_LAUNCHES), spec.get("skip_last", 0)
         disp = sorted((r for r in trace if KERNEL in r["Kernel_Name"] and int(r["Grid_Size_X"]) == grid),
-                      key=lambda r: int(r["Start_Timestamp"]))[-PROFILED_LAUNCHES:]
+                      key=lambda r: int(r["Start_Timestamp"]))
+        disp = disp[len(disp) - skip - take:len(disp) - skip]
         assert disp, f"{leg} kernel missing from the trace"
         dur = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in disp]
         st = {"Name": disp[0]["Kernel_Name"], "Calls": len(dur), "MinNs": min(dur), "MaxNs": max(dur),
@@ -174,7 +286,8 @@ def summarize_profiles(d):
             rows = counters[sub]
             k = [float(r["Counter_Value"]) for r in sorted(
                      (r for r in rows if KERNEL in r["Kernel_Name"] and int(r["Grid_Size"]) == grid),
-                     key=lambda r: int(r["Dispatch_Id"]))[-PROFILED_LAUNCHES:]]
+                     key=lambda r: int(r["Dispatch_Id"]))]
+            k = k[len(k) - skip - take:len(k) - skip]
             copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
             calib = float(copies[-1]["Counter_Value"])  # the 1 GiB copy runs last
             factor = (1 << 30) / (calib * 1024.0)       # bytes per counted byte
@@ -211,8 +324,27 @@ def summarize_profiles(d):
             for c, v in per.items():
                 f.write(f"| {c} | {v['kib_per_dispatch']:.1f} | {v['copy_1GiB_kib']:.1f} | "
                         f"{v['factor']:.4f} |\n")
+            if bench_line:
+                f.write("\n" + bench_line_note(bench_line, leg, avg_ns) + "\n")
         print(spec["trace_md"])
         print(spec["traffic"])
+
+
+def bench_line_note(path, leg, avg_ns):
+    """The same job's bench line beside a profiled kernel: its step time and
+    the leg's HIP-event mean launch duration."""
+    with open(path) as f:
+        line = json.loads([x for x in f.read().splitlines() if x.startswith("{")][-1])
+    parts = leg.split("_", 2)
+    node = (line if leg == "plain" else line.get(leg) or line.get("variants", {}).get(leg)
+            or line.get("config4", {}).get("_".join(parts[1:])) or {})
+    roof = node.get("roofline", {})
+    mean_ms = (roof.get("algorithmic_bytes_per_launch", 0) / (roof["achieved"] * 1e9) * 1e3
+               if roof.get("achieved") else None)
+    return (f"Bench line of the same job (`python3 bench.py`, unprofiled): ms_per_step "
+            f"{node.get('ms_per_step')} ms, HIP-event mean launch "
+            f"{'%.4f' % mean_ms if mean_ms else 'n/a'} ms; profiled average "
+            f"{avg_ns / 1e6:.4f} ms.")
 
 
 def timed(step, steps, warmup, stream):
@@ -344,6 +476,107 @@ def serving_leg(bfm, dev, requests=2000, payloads=32, slots=4, load=0.8, seed=5)
                        "pixels_total": pixels}}
 
 
+def latency_leg(bfm, dev, stream, calls=200, seed=1):
+    """Tile latency at the small tile of the first configuration: 64x64 pixels,
+    N = 228, n = 114 (H = 28), k = 3, one call per tile, per-call HIP events.
+    Warm: calls back to back on a resident tile.  Cold: before each call the
+    L2 caches and the MALL are flushed by writing a 1 GiB buffer (outside the
+    events), so the call reads its 3.7 MB from HBM."""
+    import torch
+
+    from paper_1807_01751_amd.synth import make_series
+    Pl, Nl, nl = 4096, 228, 114
+    Y, _ = make_series(Pl, Nl, nl, ORDER, seed=seed, device=dev)
+    out = {"brk": torch.empty(Pl, dtype=torch.int32, device=dev),
+           "mag": torch.empty(Pl, dtype=torch.float32, device=dev)}
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+
+    def step():
+        bfm.fit_monitor(Y, n=nl, order=ORDER, freq=FREQ, h=H_FRAC, lam=LAM, outputs=("brk", "mag"),
+                        out_dtype=torch.float32, out=out)
+
+    res = {}
+    for mode in ("warm", "cold"):
+        for _ in range(10):
+            step()
+        torch.cuda.synchronize()
+        lat = []
+        for _ in range(calls):
+            if mode == "cold":
+                flush.fill_(1.0)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            step()
+            b.record(stream)
+            b.synchronize()
+            lat.append(a.elapsed_time(b))
+        lat.sort()
+        q = lambda f: lat[min(len(lat) - 1, int(round(f * (len(lat) - 1))))]
+        res[mode] = {"p50_ms": round(q(0.5), 5), "p99_ms": round(q(0.99), 5), "calls": calls}
+        log(f"bench: latency tile ({mode}) p50 {q(0.5) * 1e3:.1f} us, p99 {q(0.99) * 1e3:.1f} us")
+    res["config"] = {"workload": "64x64 = 4096 pixels, N=228 FP32 observations, n=114, k=3 (p=8), "
+                                 "h=0.25 (H=28), lambda=2.5, f=23, 20% planted steps; one call per "
+                                 "tile; cold = L2 and MALL flushed by a 1 GiB write before each call"}
+    del flush
+    return res
+
+
+def config4_leg(bfm, dev, stream, warmup, steps=5):
+    """The largest tile: 4096x4096 = 16,777,216 pixels, N = 512, n = 256,
+    h = 0.25 (H = 64), 10% missing as NaN (half iid, half cloud runs of 3-15
+    rows), harmonic orders 3 and 4 (p = 8 and 10), series stored as float32 and
+    as FP16; the missing-value kernel, FP64 arithmetic.  The missing-value mask
+    is drawn per slab of 2^20 pixels (the generator's temporaries stay small)."""
+    import numpy as np
+    import torch
+
+    from paper_1807_01751_amd.synth import apply_missing, make_missing, make_series, split_rate
+    P4, N4, n4 = 1 << 24, 512, 256
+    r = split_rate(0.1)
+    rng = np.random.default_rng(44)
+    idx = np.unique(np.r_[np.arange(32), np.arange(P4 - 32, P4), rng.integers(0, P4, 4032)])
+    res = {}
+    for order in (3, 4):
+        Y, _ = make_series(P4, N4, n4, order, seed=40 + order, device=dev)
+        for s0 in range(0, P4, 1 << 20):
+            apply_missing(Y[:, s0:s0 + (1 << 20)],
+                          make_missing(N4, 1 << 20, iid=r, runs=r, seed=400 + s0 // (1 << 20), device=dev))
+        miss = float(torch.isnan(Y[:, :: 4096]).float().mean())
+        out = {"brk": torch.empty(P4, dtype=torch.int32, device=dev),
+               "mag": torch.empty(P4, dtype=torch.float32, device=dev)}
+        for name, Yd in (("f32", Y), ("f16", None)):
+            if Yd is None:
+                Yd = Y.to(torch.float16)
+
+            def step():
+                bfm.fit_monitor(Yd, n=n4, order=order, freq=FREQ, h=H_FRAC, lam=LAM, mask_mode=bfm.MASK_NAN,
+                                outputs=("brk", "mag"), out_dtype=torch.float32, out=out)
+
+            t = timed(step, steps, min(warmup, 2), stream)
+            yb = 4 if name == "f32" else 2
+            alg = (yb * N4 + 8) * P4
+            key = f"k{2 + 2 * order}_{name}"
+            res[key] = {"value": round(P4 / (t["ms_per_step"] * 1e-3) / 1e6, 2), "unit": "Mpixel/s",
+                        "ms_per_step": round(t["ms_per_step"], 4), "p50_ms": round(t["p50"], 4),
+                        "p99_ms": round(t["p99"], 4), "storage": name, "p": 2 + 2 * order,
+                        "missing_fraction": round(miss, 4),
+                        "roofline": {"bound": "hbm", "achieved": round(alg / (t["mean"] * 1e-3) / 1e9, 1),
+                                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": round(alg / (t["mean"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                     "algorithmic_bytes_per_launch": alg}}
+            log(f"bench: config 4 {key}: {t['ms_per_step']:.3f} ms/step, kernel mean {t['mean']:.3f} ms")
+            gpu_sample(f"config4_{key}", bfm, Yd, idx, n_hist=n4, lam=LAM, mask_mode=bfm.MASK_NAN,
+                       mosum=False, ref=f"config4_k{2 + 2 * order}_f32" if name == "f16" else None,
+                       order=order, freq=FREQ, h=H_FRAC)
+            del Yd
+        del Y, out
+        torch.cuda.empty_cache()
+    res["config"] = {"workload": "4096x4096 = 16777216 pixels, N=512, n=256, h=0.25 (H=64), lambda=2.5, "
+                                 "f=23, 10% NaN (half iid, half cloud runs of 3-15 rows), p=8 and 10, "
+                                 "float32 and FP16 storage, FP64 arithmetic"}
+    return res
+
+
 def roofline(leg, mean_ms, y_bytes=4):
     spec = LEGS[leg]
     bytes_per_px = y_bytes * spec.get("n_obs", N) + 4 + 4  # read y once; write int32 brk + FP32 mag
@@ -363,14 +596,18 @@ def main():
     ap.add_argument("--prewarm-s", type=float, default=0.25,
                     help="seconds of untimed steps before the warmup steps (clock ramp)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="leave out the serving leg (the profiling runs: no summary uses it)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="write profiles/ summaries from rocprofv3 output under DIR and exit")
+    ap.add_argument("--bench-line", metavar="FILE",
+                    help="with --summarize-profiles: the JSON line of an unprofiled run of the same job")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, run one 1 GiB device-to-device copy (the known-size "
                          "reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.summarize_profiles:
-        summarize_profiles(args.summarize_profiles)
+        summarize_profiles(args.summarize_profiles, args.bench_line)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -410,6 +647,10 @@ def main():
     tp = timed(step, args.steps, args.warmup, stream)
     log(f"bench: {tp['ms_per_step']:.4f} ms/step wall, kernel mean {tp['mean']:.4f} ms")
     ref = {k: v.clone() for k, v in out.items()}
+    import numpy as np
+    idx = np.arange(0, P, ACC_STRIDE)  # pixels checked against the oracle
+    common = dict(order=ORDER, freq=FREQ, h=H_FRAC)
+    gpu_sample("plain", bfm, Y, idx, n_hist=n, lam=LAM, **common)
 
     # Mixed-precision leg: FP16-stored tile, FP64 arithmetic.
     Yh = Y.to(torch.float16)
@@ -427,6 +668,7 @@ def main():
     # largest and the smallest MOSUM values are nearly opposite, the signed
     # magnitude may flip sign between the two runs.
     dmag = float((outh["mag"].abs() - ref["mag"].abs()).abs().max())
+    gpu_sample("mixed", bfm, Yh, idx, n_hist=n, lam=LAM, ref="plain", **common)
     del Yh
 
     # Masked leg: the same tile with NaN at 25% of (time, pixel) positions.
@@ -442,6 +684,7 @@ def main():
     log(f"bench: masked leg ({miss:.3f} missing), warmup {args.warmup}, timing {args.steps} steps")
     tm = timed(mstep, args.steps, args.warmup, stream)
     log(f"bench: masked {tm['ms_per_step']:.4f} ms/step wall, kernel mean {tm['mean']:.4f} ms")
+    gpu_sample("masked", bfm, Ym, idx, n_hist=n, lam=LAM, mask_mode=bfm.MASK_NAN, **common)
     del Ym
 
     # Fill leg: 10% missing (half iid, half cloud runs), filled forward as read.
@@ -455,6 +698,7 @@ def main():
     log(f"bench: fill leg, warmup {args.warmup}, timing {args.steps} steps")
     tf = timed(fstep, args.steps, args.warmup, stream)
     log(f"bench: fill {tf['ms_per_step']:.4f} ms/step wall, kernel mean {tf['mean']:.4f} ms")
+    gpu_sample("fill", bfm, Yf, idx, n_hist=n, lam=LAM, mask_mode=bfm.MASK_FILL, **common)
     del Yf
 
     # Irregular-time leg: a scene of the Chile experiment's shape at synthetic
@@ -473,7 +717,12 @@ def main():
     log(f"bench: times leg ({CHILE_P} pixels x {CHILE_N} days), timing {max(5, args.steps // 5)} steps")
     tc = timed(cstep, max(5, args.steps // 5), min(args.warmup, 2), stream)
     log(f"bench: times {tc['ms_per_step']:.4f} ms/step wall, kernel mean {tc['mean']:.4f} ms")
+    gpu_sample("times", bfm, Yc, np.arange(0, CHILE_P, 4 * ACC_STRIDE), n_hist=CHILE_n, lam=LAM,
+               order=ORDER, freq=365.0, h_window=CHILE_H, times=days)
     del Yc, outc
+
+    latency = latency_leg(bfm, dev, stream)
+    config4 = config4_leg(bfm, dev, stream, args.warmup)
 
     # Critical value by simulation: one million no-change paths at n = 200, N = 400, H = 50.
     def lstep():
@@ -486,10 +735,12 @@ def main():
     log(f"bench: lambda {lam_crit:.5f} from {LAMBDA_PATHS} paths: sup kernel {tl['mean']:.3f} ms, "
         f"call {lam_ms:.2f} ms")
 
-    log("bench: serving leg (Poisson arrivals, continuous batching)")
-    serving = serving_leg(bfm, dev)
-    log(f"bench: serving {serving['mpixel_s']} Mpixel/s, p50 {serving['p50_ms']} ms, "
-        f"p99 {serving['p99_ms']} ms, max running {serving['max_running']}")
+    serving = None
+    if not args.no_serving:
+        log("bench: serving leg (Poisson arrivals, continuous batching)")
+        serving = serving_leg(bfm, dev)
+        log(f"bench: serving {serving['mpixel_s']} Mpixel/s, p50 {serving['p50_ms']} ms, "
+            f"p99 {serving['p99_ms']} ms, max running {serving['max_running']}")
 
     # Context (not the metric): the tile's host-to-device transfer from pinned
     # memory, the phase that dominates the paper's GPU timings.
@@ -570,9 +821,17 @@ def main():
                    "gb_per_s": round(4 * N * P / (h2d_ms * 1e-3) / 1e9, 1),
                    "pcie_inclusive_mpixel_s": round(P / ((h2d_ms + tp["mean"]) * 1e-3) / 1e6, 1),
                    "note": "pinned host tile to device, median of 3; context only"}}
+    res["latency_tile"] = latency
+    res["config4"] = config4
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
         res["cpu_baseline"] = cpu_baseline(Y, args.cpu_seconds)
+        res["accuracy"] = check_samples(res["cpu_baseline"]["cores"])
+        res["accuracy"]["note"] = (
+            "FP64 oracle against the GPU's FP64 outputs of each leg's kernels on sampled "
+            f"pixels (every {ACC_STRIDE}th pixel of the 1024x1024 tiles, every {4 * ACC_STRIDE}th "
+            "of the Chile-shaped scene, 4096 of each 16.8M-pixel config-4 tile); 16-bit legs "
+            "against the oracle on the values they decode to")
     print(json.dumps(res), flush=True)
 
 
