@@ -330,6 +330,54 @@ def summarize_profiles(d, bench_line=None):
         print(spec["traffic"])
 
 
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_WAVE_CYCLES",
+               "SQ_ACTIVE_INST_VALU", "SQ_WAIT_INST_ANY", "SQ_BUSY_CYCLES")
+
+
+SQ_CMD = ("rocprofv3 --pmc " + " ".join(SQ_COUNTERS) + " -f csv -d <dir>/sq -o run -- python3 bench.py "
+          "--steps 10 --warmup 2 --no-cpu-baseline --no-serving > <dir>/sq.log 2>&1")
+
+
+def summarize_sq(d):
+    """Instruction counters of each leg's kernel (one rocprofv3 --pmc pass of
+    the eight SQ counters under ``d``/sq) into profiles/sq_counters.md: per
+    wave and per row of the series, and the share of a wave's cycles spent
+    issuing VALU instructions or waiting."""
+    import collections
+    import glob
+    import re
+    with open(os.path.join(d, "sq.log")) as f:
+        shas = set(re.findall(r"kernel_sha=([0-9a-f]+)", f.read()))
+    assert shas == {kernel_sha()}, f"counters were taken on other sources: {shas}"
+    rows = _csv(glob.glob(os.path.join(d, "sq", "*counter_collection.csv"))[0])
+    out = os.path.join(PROFILES, "sq_counters.md")
+    with open(out, "w") as f:
+        f.write("# SQ instruction counters per kernel\n\nCommand (from the repository root, on one "
+                "MI355X):\n\n    " + SQ_CMD
+                + "\n\nAverages over each leg's last ten whole-workload launches. Per row = per "
+                "wave / N (one lane per pixel, one row per observation). VALU share = "
+                "SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES, wait share = SQ_WAIT_INST_ANY / "
+                "SQ_WAVE_CYCLES (both per wave).\n\n| leg | kernel | waves | VALU / wave | SALU / wave "
+                "| LDS / wave | VALU / row | SALU / row | VALU share | wait share |\n"
+                "|---|---|---|---|---|---|---|---|---|---|\n")
+        for leg, spec in LEGS.items():
+            grid = (spec.get("pixels", P) + 63) // 64 * 64
+            per = collections.defaultdict(list)
+            for r in rows:
+                if spec["kernel"] in r["Kernel_Name"] and int(r["Grid_Size"]) == grid:
+                    per[r["Counter_Name"]].append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+            if not per:
+                continue
+            avg = {c: sum(v for _, v in sorted(x)[-10:]) / len(sorted(x)[-10:]) for c, x in per.items()}
+            w, nobs = avg["SQ_WAVES"], spec.get("n_obs", N)
+            f.write(f"| {leg} | {spec['kernel'].strip(':(')} | {w:.0f} | {avg['SQ_INSTS_VALU'] / w:.0f} | "
+                    f"{avg['SQ_INSTS_SALU'] / w:.0f} | {avg['SQ_INSTS_LDS'] / w:.0f} | "
+                    f"{avg['SQ_INSTS_VALU'] / w / nobs:.1f} | {avg['SQ_INSTS_SALU'] / w / nobs:.1f} | "
+                    f"{avg['SQ_ACTIVE_INST_VALU'] / avg['SQ_WAVE_CYCLES']:.3f} | "
+                    f"{avg['SQ_WAIT_INST_ANY'] / avg['SQ_WAVE_CYCLES']:.3f} |\n")
+    print(out)
+
+
 def bench_line_note(path, leg, avg_ns):
     """The same job's bench line beside a profiled kernel: its step time and
     the leg's HIP-event mean launch duration."""
@@ -607,7 +655,10 @@ def main():
                          "reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.summarize_profiles:
-        summarize_profiles(args.summarize_profiles, args.bench_line)
+        if os.path.isdir(os.path.join(args.summarize_profiles, "sq")):
+            summarize_sq(args.summarize_profiles)
+        if os.path.isdir(os.path.join(args.summarize_profiles, "trace")):
+            summarize_profiles(args.summarize_profiles, args.bench_line)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -150,15 +150,17 @@ struct FlaggedObs {
     uint32_t ok;
 };
 
-struct FlaggedCursor {
+template <typename T>
+struct FlaggedCursorT {
     using value_type = FlaggedObs;
-    const float* row;
+    const T* row;
     const uint8_t* vrow;
     int64_t ld, ldv;
     uint32_t lane;
     __device__ __forceinline__ value_type load(int u) const
     {
-        return {load_obs(row + (int64_t)u * ld, lane * 4u), load_flag(vrow + (int64_t)u * ldv, lane)};
+        return {load_obs(row + (int64_t)u * ld, lane * (uint32_t)sizeof(T)),
+                load_flag(vrow + (int64_t)u * ldv, lane)};
     }
     __device__ __forceinline__ void advance(int k)
     {
@@ -166,6 +168,7 @@ struct FlaggedCursor {
         vrow += (int64_t)k * ldv;
     }
 };
+using FlaggedCursor = FlaggedCursorT<float>;
 
 // Streams rows [t0, t1) of one pixel column; `cur` must point at row t0.
 // Rows are fetched in chunks of U, one chunk ahead of the arithmetic, with two

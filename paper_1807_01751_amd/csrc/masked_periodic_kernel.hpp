@@ -386,32 +386,31 @@ masked_periodic_kernel(MaskedArgs a)
     double rss = yy - zz;
     const bool refine = fitted && rss < kRefineRatio * yy;
     if (__ballot(refine) != 0) {
+        // Design rows from the table of the general kernel (the same basis:
+        // tau = (t - c0) / n, harmonics at 1-based time), rows streamed in
+        // chunks of eight: a lean loop, so that the factor L can stay live.
         double dq[NP], rr = 0.0;
 #pragma unroll
         for (int j = 0; j < NP; ++j) dq[j] = 0.0;
-        stream_blocks<F>(
-            [&](int t) { return Cur::at(a, t, lane); }, 0, n,
-            [&](int u, int t, V val, bool in) {
-                if (in && observed(val)) {
-                    const double tau = ((double)t - c0) * inv_n;
-                    double f = fma(beta[1], tau, beta[0]);
+        const ctab x = as_const(a.x);
+        auto row2 = [&](int t, float v, bool used) {
+            if (used) {
+                const ctab xr = x + t * NP;
+                double r = (double)v - c;
 #pragma unroll
-                    for (int j = 1; j <= K; ++j) {
-                        f = fma(beta[2 * j], ph[u * NT + 2 * (j - 1)], f);
-                        f = fma(beta[2 * j + 1], ph[u * NT + 2 * (j - 1) + 1], f);
-                    }
-                    const double r = ((double)value(val) - c) - f;
-                    rr = fma(r, r, rr);
-                    dq[0] += r;
-                    dq[1] = fma(tau, r, dq[1]);
+                for (int j = 0; j < NP; ++j) r = fma(-xr[j], beta[j], r);
+                rr = fma(r, r, rr);
 #pragma unroll
-                    for (int j = 1; j <= K; ++j) {
-                        dq[2 * j] = fma(ph[u * NT + 2 * (j - 1)], r, dq[2 * j]);
-                        dq[2 * j + 1] = fma(ph[u * NT + 2 * (j - 1) + 1], r, dq[2 * j + 1]);
-                    }
-                }
-            },
-            [](int) {}, [](const V*) {});
+                for (int j = 0; j < NP; ++j) dq[j] = fma(xr[j], r, dq[j]);
+            }
+        };
+        const T* const Yt = static_cast<const T*>(a.Y);
+        if (EXPLICIT)
+            stream_rows<8>(FlaggedCursorT<T>{Yt, a.valid, a.ld, a.ldv, lane}, 0, n,
+                           [&](int t, FlaggedObs o) { row2(t, o.y, o.ok != 0); });
+        else
+            stream_rows<8>(ObsCursorT<T>{Yt, a.ld, lane * (uint32_t)sizeof(T)}, 0, n,
+                           [&](int t, float v) { row2(t, v, isfinite(v)); });
         rss = refine ? rr - Gk::refine(L, dq, beta, refine) : rss;
     }
     const double sig = sqrt(fmax(rss, 0.0) / (double)(nv - NP));
