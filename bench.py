@@ -30,7 +30,9 @@ Two more legs follow: the small tile of the first configuration (64 x 64
 pixels, N = 228) timed call by call, warm and with the L2 caches and the MALL
 flushed before each call ("latency_tile"), and the largest tile (4096 x 4096
 pixels, N = 512, 10% NaN, p = 8 and 10, float32 and FP16 storage) on the
-missing-value kernel ("config4").  In the CPU-baseline leg the oracle also
+missing-value kernel ("config4").  The masked tile and the p = 8 config-4
+tiles are also timed with the MOSUM in FP32 (BFM_PREC_FP32: "masked_fp32",
+"config4" keys ending in _fp32).  In the CPU-baseline leg the oracle also
 checks sampled pixels of every leg against the GPU's FP64 outputs of the same
 kernels ("accuracy": sigma, magnitude and MOSUM errors, break agreement,
 marginal and non-marginal break mismatches).
@@ -66,7 +68,7 @@ LEGS = {
               "traffic": os.path.join(PROFILES, "traffic_mixed_f16_1024x1024_N400.json"),
               "trace_md": os.path.join(PROFILES, "mixed_periodic_f16_k3_f23_1024x1024_N400_kernel_trace.md"),
               "workload": "1024x1024 pixels, N=400, FP16-stored", "y_bytes": 2},
-    "masked": {"kernel": "::masked_periodic_kernel<3, 23, false, false, float>(",
+    "masked": {"kernel": "::masked_periodic_kernel<3, 23, false, false, float, false>(",
                "traffic": os.path.join(PROFILES, "traffic_masked_1024x1024_N400_nan25.json"),
                "trace_md": os.path.join(PROFILES,
                                         "masked_periodic_k3_f23_1024x1024_N400_nan25_kernel_trace.md"),
@@ -85,7 +87,7 @@ for _k, _ord in (("k8", 3), ("k10", 4)):
     for _st, _yb in (("f32", 4), ("f16", 2)):
         _T = "float" if _st == "f32" else "bfm::dev::f16_t"
         LEGS[f"config4_{_k}_{_st}"] = {
-            "kernel": f"::masked_periodic_kernel<{_ord}, 23, false, false, {_T}>(",
+            "kernel": f"::masked_periodic_kernel<{_ord}, 23, false, false, {_T}, false>(",
             "traffic": os.path.join(PROFILES, f"traffic_config4_{_k}_{_st}_4096x4096_N512_nan10.json"),
             "trace_md": os.path.join(PROFILES, f"config4_masked_periodic_{_k}_{_st}_4096x4096_N512_nan10"
                                                 "_kernel_trace.md"),
@@ -93,6 +95,20 @@ for _k, _ord in (("k8", 3), ("k10", 4)):
             "pixels": 1 << 24, "n_obs": 512, "y_bytes": _yb,
             # 5 timed and 5 latency-pass launches, then the untimed FP64 sample call
             "launches": 10, "skip_last": 1}
+LEGS["masked_fp32"] = {
+    "kernel": "::masked_periodic_kernel<3, 23, false, false, float, true>(",
+    "traffic": os.path.join(PROFILES, "traffic_masked_fp32_1024x1024_N400_nan25.json"),
+    "trace_md": os.path.join(PROFILES, "masked_periodic_fp32_k3_f23_1024x1024_N400_nan25_kernel_trace.md"),
+    "workload": "1024x1024 pixels, N=400, 25% NaN, MOSUM in FP32"}
+for _st, _yb in (("f32", 4), ("f16", 2)):
+    _T = "float" if _st == "f32" else "bfm::dev::f16_t"
+    LEGS[f"config4_k8_{_st}_fp32"] = {
+        "kernel": f"::masked_periodic_kernel<3, 23, false, false, {_T}, true>(",
+        "traffic": os.path.join(PROFILES, f"traffic_config4_k8_{_st}_fp32_4096x4096_N512_nan10.json"),
+        "trace_md": os.path.join(PROFILES, f"config4_masked_periodic_fp32_k8_{_st}_4096x4096_N512_nan10"
+                                            "_kernel_trace.md"),
+        "workload": f"4096x4096 pixels, N=512, 10% NaN, p=8, {_st} storage, MOSUM in FP32",
+        "pixels": 1 << 24, "n_obs": 512, "y_bytes": _yb, "launches": 10, "skip_last": 1}
 CHILE_P, CHILE_N, CHILE_n, CHILE_H = 2400 * 1851, 288, 144, 72
 FILL_MISSING = 0.10
 LAMBDA_PATHS = 1 << 20
@@ -592,36 +608,41 @@ def config4_leg(bfm, dev, stream, warmup, steps=5):
         miss = float(torch.isnan(Y[:, :: 4096]).float().mean())
         out = {"brk": torch.empty(P4, dtype=torch.int32, device=dev),
                "mag": torch.empty(P4, dtype=torch.float32, device=dev)}
-        for name, Yd in (("f32", Y), ("f16", None)):
-            if Yd is None:
-                Yd = Y.to(torch.float16)
+        runs = [("f32", "fp64"), ("f16", "fp64")]
+        if order == 3:
+            runs += [("f32", "fp32"), ("f16", "fp32")]
+        Yh = Y.to(torch.float16)
+        for name, prec in runs:
+            Yd = Y if name == "f32" else Yh
 
             def step():
                 bfm.fit_monitor(Yd, n=n4, order=order, freq=FREQ, h=H_FRAC, lam=LAM, mask_mode=bfm.MASK_NAN,
-                                outputs=("brk", "mag"), out_dtype=torch.float32, out=out)
+                                outputs=("brk", "mag"), out_dtype=torch.float32, out=out, precision=prec)
 
             t = timed(step, steps, min(warmup, 2), stream)
             yb = 4 if name == "f32" else 2
             alg = (yb * N4 + 8) * P4
-            key = f"k{2 + 2 * order}_{name}"
+            key = f"k{2 + 2 * order}_{name}" + ("_fp32" if prec == "fp32" else "")
             res[key] = {"value": round(P4 / (t["ms_per_step"] * 1e-3) / 1e6, 2), "unit": "Mpixel/s",
                         "ms_per_step": round(t["ms_per_step"], 4), "p50_ms": round(t["p50"], 4),
                         "p99_ms": round(t["p99"], 4), "storage": name, "p": 2 + 2 * order,
+                        "mosum": "f32" if prec == "fp32" else "f64",
                         "missing_fraction": round(miss, 4),
                         "roofline": {"bound": "hbm", "achieved": round(alg / (t["mean"] * 1e-3) / 1e9, 1),
                                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                      "frac": round(alg / (t["mean"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                      "algorithmic_bytes_per_launch": alg}}
             log(f"bench: config 4 {key}: {t['ms_per_step']:.3f} ms/step, kernel mean {t['mean']:.3f} ms")
+            ref = None if key == f"k{2 + 2 * order}_f32" else f"config4_k{2 + 2 * order}_f32"
             gpu_sample(f"config4_{key}", bfm, Yd, idx, n_hist=n4, lam=LAM, mask_mode=bfm.MASK_NAN,
-                       mosum=False, ref=f"config4_k{2 + 2 * order}_f32" if name == "f16" else None,
-                       order=order, freq=FREQ, h=H_FRAC)
+                       mosum=False, ref=ref, order=order, freq=FREQ, h=H_FRAC, precision=prec)
             del Yd
-        del Y, out
+        del Y, Yh, out
         torch.cuda.empty_cache()
     res["config"] = {"workload": "4096x4096 = 16777216 pixels, N=512, n=256, h=0.25 (H=64), lambda=2.5, "
                                  "f=23, 10% NaN (half iid, half cloud runs of 3-15 rows), p=8 and 10, "
-                                 "float32 and FP16 storage, FP64 arithmetic"}
+                                 "float32 and FP16 storage, FP64 arithmetic; for p=8 also the MOSUM "
+                                 "in FP32 (_fp32: BFM_PREC_FP32)"}
     return res
 
 
@@ -736,6 +757,17 @@ def main():
     tm = timed(mstep, args.steps, args.warmup, stream)
     log(f"bench: masked {tm['ms_per_step']:.4f} ms/step wall, kernel mean {tm['mean']:.4f} ms")
     gpu_sample("masked", bfm, Ym, idx, n_hist=n, lam=LAM, mask_mode=bfm.MASK_NAN, **common)
+
+    # The same tile with the MOSUM in FP32 (BFM_PREC_FP32; the fit stays FP64).
+    def m32step():
+        bfm.fit_monitor(Ym, n=n, order=ORDER, freq=FREQ, h=H_FRAC, lam=LAM, mask_mode=bfm.MASK_NAN,
+                        outputs=("brk", "mag"), out_dtype=torch.float32, out=out, precision="fp32")
+
+    log(f"bench: masked leg with FP32 MOSUM, warmup {args.warmup}, timing {args.steps} steps")
+    tm32 = timed(m32step, args.steps, args.warmup, stream)
+    log(f"bench: masked FP32 {tm32['ms_per_step']:.4f} ms/step wall, kernel mean {tm32['mean']:.4f} ms")
+    gpu_sample("masked_fp32", bfm, Ym, idx, n_hist=n, lam=LAM, mask_mode=bfm.MASK_NAN, ref="masked",
+               precision="fp32", **common)
     del Ym
 
     # Fill leg: 10% missing (half iid, half cloud runs), filled forward as read.
@@ -839,6 +871,14 @@ def main():
                                              "of 3-15 rows), per-pixel Gram and Cholesky",
                                  "missing_fraction": round(miss, 4)},
                       "roofline": roofline("masked", tm["mean"])},
+           "masked_fp32": {"value": round(P / (tm32["ms_per_step"] * 1e-3) / 1e6, 2), "unit": "Mpixel/s",
+                           "ms_per_step": round(tm32["ms_per_step"], 5), "p50_ms": round(tm32["p50"], 5),
+                           "p99_ms": round(tm32["p99"], 5), "dtype": "f64 fit, f32 MOSUM",
+                           "config": {"workload": "the masked leg's tile with the MOSUM in FP32 "
+                                                  "(BFM_PREC_FP32): residuals formed in FP64 and rounded "
+                                                  "to float, window sums and boundary test in FP32; "
+                                                  "Gram, Cholesky and sigma in FP64"},
+                           "roofline": roofline("masked_fp32", tm32["mean"])},
            "mixed": {"value": round(P / (th["ms_per_step"] * 1e-3) / 1e6, 2), "unit": "Mpixel/s",
                      "ms_per_step": round(th["ms_per_step"], 5), "p50_ms": round(th["p50"], 5),
                      "p99_ms": round(th["p99"], 5), "dtype": "f64", "storage": "f16",

@@ -60,6 +60,7 @@ extern "C" {
 
 /* arithmetic of the computation */
 #define BFM_PREC_FP64 0
+#define BFM_PREC_FP32 1
 
 /* storage type of the series Y (bfm_fit_monitor_typed) */
 #define BFM_Y_F32 0  /* IEEE float32                                        */
@@ -92,7 +93,18 @@ extern "C" {
  *             (with missing values: floor(h_frac * n_v)); 0 < h_frac <= 1.
  *   lambda    critical value of the boundary (Eq. 4), > 0.
  *   mask_mode one of BFM_MASK_*.
- *   precision BFM_PREC_FP64.
+ *   precision BFM_PREC_FP64, or BFM_PREC_FP32: the MOSUM of the
+ *             period-blocked missing-value path (f in {12, 23, 24}, float32 or
+ *             FP16 series) in FP32, as in the paper's own float MOSUM kernel:
+ *             each residual is formed in FP64 and rounded to float, and the
+ *             window sums, their extremes and the boundary test run in FP32;
+ *             the fit (Gram matrix, Cholesky factor, coefficients) and sigma
+ *             stay FP64.  Results agree with FP64 to about 1e-6 (relative);
+ *             a break index may differ where the MOSUM is within about 1e-4
+ *             (relative) of the boundary.  Every other path (complete series,
+ *             BF16 storage, other f, observation times) computes in FP64
+ *             under either setting: those paths are bound by reading the
+ *             series, and on gfx950 FP32 instructions issue at the FP64 rate.
  *   times     host, NULL or N doubles, finite and strictly increasing: the
  *             time of each observation, used in place of the index t in the
  *             design rows of Eq. 2 (Section 4 does this with day numbers and
@@ -296,11 +308,14 @@ int bfm_critical_value_noalloc(bfm_ctx *ctx, const bfm_params *prm, double alpha
  * arrive, several at a time: each admitted request runs on one of `slots` HIP
  * streams of the server's device (non-blocking, default priority), so the work
  * of requests that arrive while others are on the GPU overlaps with theirs.  A
- * request is admitted, in arrival order, when a stream is free and its outputs
+ * request is admitted, in arrival order, when a stream is free, its outputs
  * fit in the server's device pool (pool_bytes, allocated once at creation: no
- * allocation happens per request).  The shared operators of each parameter set
- * are built once and stay on the device (Section 3 builds the shared matrix
- * once for all pixels).  Results are exactly those of bfm_fit_monitor_typed on
+ * allocation happens per request) and, for a parameter set not yet cached, its
+ * operator block fits in the operator budget next to the blocks that running
+ * requests read (the admission is by HBM footprint: outputs plus operators).
+ * The shared operators of each parameter set are built once and stay on the
+ * device while the budget allows (Section 3 builds the shared matrix once for
+ * all pixels); see bfm_operator_budget for their eviction.  Results are exactly those of bfm_fit_monitor_typed on
  * the same request.  Thread-safe: any host thread may submit, wait and release.
  */
 typedef struct bfm_server bfm_server;
@@ -354,9 +369,17 @@ int bfm_request_bytes(const bfm_request *req, size_t *bytes);
 int bfm_server_create(bfm_server **out, int device, int slots, size_t pool_bytes);
 
 /*
+ * The server's operator budget (bfm_operator_budget on its context; default
+ * 64 MiB), set before the first request.  Errors: BFM_E_INVAL (NULL server,
+ * or requests were submitted already).
+ */
+int bfm_server_operator_budget(bfm_server *s, size_t bytes);
+
+/*
  * Queue a request; returns at once with a ticket (> 0).  Parameters are
  * validated here: BFM_E_INVAL / BFM_E_LAYOUT as for bfm_fit_monitor_typed, and
- * BFM_E_NOMEM if the request's outputs exceed the whole pool.  Errors found at
+ * BFM_E_NOMEM if the request's outputs exceed the whole pool or its operator
+ * block the whole operator budget.  Errors found at
  * launch (e.g. BFM_E_UNSUPPORTED) are reported in the result.
  */
 int bfm_server_submit(bfm_server *s, const bfm_request *req, uint64_t *ticket);
@@ -383,13 +406,19 @@ int bfm_server_release(bfm_server *s, uint64_t ticket);
 int bfm_server_take(bfm_server *s, uint64_t ticket, const bfm_outputs *dst, void *stream);
 
 /* Counters of a server: requests queued, running and completed-unreleased,
- * pool bytes in use, and the largest number of requests that ran at once. */
+ * pool bytes in use, the largest number of requests that ran at once, its
+ * operator cache (blocks, bytes, evictions), and how many requests waited at
+ * the head of the queue for room in the operator budget. */
 typedef struct {
     int64_t queued;
     int64_t running;
     int64_t completed;
     int64_t pool_in_use;
     int64_t max_running;
+    int64_t operator_entries;
+    int64_t operator_bytes;
+    int64_t operator_evictions;
+    int64_t operator_waits;
 } bfm_server_stats;
 int bfm_server_get_stats(bfm_server *s, bfm_server_stats *st);
 
@@ -429,6 +458,29 @@ int bfm_host_operators(const bfm_params *prm, double *q, double *w, double *bnd,
  * Errors: BFM_E_INVAL (bad parameters, out NULL), BFM_E_LAYOUT.
  */
 int bfm_workspace_bytes(const bfm_params *prm, int64_t P, size_t *out);
+
+/*
+ * Operator cache of a context.  The operator blocks of the parameter sets a
+ * context has run (Section 3 forms the shared matrix once for all pixels) live
+ * in one device arena of `budget` bytes (default 64 MiB), allocated at the
+ * first call and carved first-fit.  When a new block does not fit, least
+ * recently used blocks are evicted, idle ones first; a block is returned only
+ * once the last launch that reads it has finished (a wait on that launch's
+ * event alone: work on other streams goes on).  A block larger than the whole
+ * budget gets a device allocation of its own.
+ * bfm_operator_budget sets the budget; it must come before the first call on
+ * the context (BFM_E_INVAL after).  bfm_cache_get_stats reports the cached
+ * blocks, their bytes, the budget and the evictions so far.
+ * Errors: BFM_E_INVAL (NULL arguments, budget set too late).
+ */
+typedef struct {
+    int64_t entries;
+    int64_t bytes;
+    int64_t budget;
+    int64_t evictions;
+} bfm_cache_stats;
+int bfm_operator_budget(bfm_ctx *ctx, size_t bytes);
+int bfm_cache_get_stats(bfm_ctx *ctx, bfm_cache_stats *st);
 
 #ifdef __cplusplus
 }

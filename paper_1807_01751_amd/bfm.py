@@ -23,7 +23,8 @@ SUCCESS = 0
 E_INVAL, E_LAYOUT, E_NOMEM, E_NODEVICE, E_HIP, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
 MASK_NONE, MASK_NAN, MASK_EXPLICIT, MASK_FILL = 0, 1, 2, 3
 NOALLOC_MAX_PATHS = 4194304  # BFM_NOALLOC_MAX_PATHS
-PREC_FP64 = 0
+PREC_FP64, PREC_FP32 = 0, 1
+_PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32}
 Y_F32, Y_BF16, Y_F16 = 0, 1, 2
 _Y_DTYPES = {torch.float32: Y_F32, torch.bfloat16: Y_BF16, torch.float16: Y_F16}
 OUT_F32, OUT_F64 = 0, 1
@@ -38,7 +39,8 @@ EXPORTS = ("bfm_version", "bfm_last_error", "bfm_check_params", "bfm_create", "b
            "bfm_server_create", "bfm_server_submit", "bfm_server_wait", "bfm_server_release",
            "bfm_server_take", "bfm_autotune", "bfm_tune_set", "bfm_mosum_null_sup",
            "bfm_critical_value", "bfm_critical_value_noalloc", "bfm_workspace_bytes",
-           "bfm_server_get_stats", "bfm_server_destroy")
+           "bfm_server_get_stats", "bfm_server_destroy", "bfm_operator_budget", "bfm_cache_get_stats",
+           "bfm_server_operator_budget")
 WANT = {"mag": 1, "sigma": 2, "status": 4, "beta": 8, "resid": 16, "mosum": 32}
 
 
@@ -102,7 +104,12 @@ class Result(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("queued", "running", "completed", "pool_in_use",
-                                             "max_running")]
+                                             "max_running", "operator_entries", "operator_bytes",
+                                             "operator_evictions", "operator_waits")]
+
+
+class CacheStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("entries", "bytes", "budget", "evictions")]
 
 
 _lib = None
@@ -147,6 +154,9 @@ def load():
     lib.bfm_server_take.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Outputs), vp]
     lib.bfm_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib.bfm_server_destroy.argtypes = [vp]
+    lib.bfm_operator_budget.argtypes = [vp, ctypes.c_size_t]
+    lib.bfm_cache_get_stats.argtypes = [vp, ctypes.POINTER(CacheStats)]
+    lib.bfm_server_operator_budget.argtypes = [vp, ctypes.c_size_t]
     _lib = lib
     return lib
 
@@ -160,9 +170,17 @@ def version() -> int:
     return load().bfm_version()
 
 
+def cache_stats(device: int = 0) -> dict:
+    """bfm_cache_get_stats of the device's context: cached operator blocks,
+    their bytes, the budget and the evictions so far."""
+    st = CacheStats()
+    _raise(load().bfm_cache_get_stats(context(device), ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in CacheStats._fields_}
+
+
 def make_params(N: int, n: int, order: int = 3, freq: float = 23.0, h: float = 0.25,
                 h_window: int = 0, lam: float = 2.5, mask_mode: int = MASK_NONE,
-                times=None) -> Params:
+                times=None, precision="fp64") -> Params:
     """bfm_params.  ``times`` (N observation times, host) is copied into a
     float64 array that the returned struct keeps alive."""
     keep = None
@@ -171,7 +189,7 @@ def make_params(N: int, n: int, order: int = 3, freq: float = 23.0, h: float = 0
         if keep.shape != (int(N),):
             raise ValueError(f"times must hold N = {N} values")
     prm = Params(int(N), int(n), int(order), int(h_window), float(freq), float(h), float(lam),
-                 int(mask_mode), PREC_FP64,
+                 int(mask_mode), _PRECISIONS.get(precision, precision),
                  None if keep is None else keep.ctypes.data_as(ctypes.c_void_p))
     prm._times = keep
     return prm
@@ -237,7 +255,7 @@ def fit_monitor(Y: torch.Tensor, *, n: int, order: int = 3, freq: float = 23.0, 
                 h_window: int = 0, lam: float = 2.5, mask_mode: int = MASK_NONE,
                 valid: torch.Tensor | None = None, times=None, outputs=("brk", "mag"),
                 out_dtype: torch.dtype = torch.float64, out: dict | None = None,
-                stream: torch.cuda.Stream | None = None) -> dict:
+                stream: torch.cuda.Stream | None = None, precision="fp64") -> dict:
     """bfm_fit_monitor on a device-resident series block (float32, bfloat16 or
     float16, through bfm_fit_monitor_typed).
 
@@ -245,14 +263,16 @@ def fit_monitor(Y: torch.Tensor, *, n: int, order: int = 3, freq: float = 23.0, 
     (P, N) transpose view of such a block).  ``outputs`` names the arrays to
     produce among brk, mag, sigma, status, beta, resid, mosum; ``out`` may supply
     preallocated tensors for them.  ``times`` (N observation times, host) replaces
-    the index t in the design rows.  Work is enqueued on ``stream`` (default: the
-    current stream) and the call returns without synchronising.
+    the index t in the design rows.  ``precision`` "fp32" asks for the FP32
+    MOSUM of the period-blocked missing-value path (BFM_PREC_FP32); other
+    paths compute in FP64 either way.  Work is enqueued on ``stream``
+    (default: the current stream) and the call returns without synchronising.
     """
     if Y.dtype not in _Y_DTYPES or Y.device.type != "cuda":
         raise ValueError("Y must be a float32, bfloat16 or float16 tensor on a HIP device")
     Y, N, P, ld = _series_layout(Y)
     dev = Y.device.index if Y.device.index is not None else torch.cuda.current_device()
-    prm = make_params(N, n, order, freq, h, h_window, lam, mask_mode, times)
+    prm = make_params(N, n, order, freq, h, h_window, lam, mask_mode, times, precision)
     p = 2 + 2 * order
     shapes = {"brk": ((P,), torch.int32), "mag": ((P,), out_dtype), "sigma": ((P,), out_dtype),
               "status": ((P,), torch.uint8), "beta": ((p, P), out_dtype),
@@ -355,8 +375,10 @@ def tune_set(Y: torch.Tensor, split: int, *, n: int, order: int = 3, freq: float
 
 class Server:
     """bfm_server_*: requests of different shapes and parameters, run as they
-    arrive on ``slots`` streams of one device, admitted by free stream and by room
-    for their outputs in a device pool of ``pool_bytes`` (allocated once).
+    arrive on ``slots`` streams of one device, admitted by free stream, by room
+    for their outputs in a device pool of ``pool_bytes`` (allocated once) and by
+    room for a new parameter set's operators in ``operator_budget`` bytes
+    (default 64 MiB).
 
     ``submit`` takes the same arguments as ``fit_monitor`` (without ``out``) and
     returns a ticket at once; ``result`` waits for it and returns its outputs as
@@ -365,12 +387,15 @@ class Server:
     The caller keeps ``Y`` (and ``valid``) alive and unchanged until then.
     """
 
-    def __init__(self, device: int = 0, slots: int = 4, pool_bytes: int = 1 << 30):
+    def __init__(self, device: int = 0, slots: int = 4, pool_bytes: int = 1 << 30,
+                 operator_budget: int | None = None):
         h = ctypes.c_void_p()
         _raise(load().bfm_server_create(ctypes.byref(h), int(device), int(slots), int(pool_bytes)))
         self.handle = h.value
         self.device = torch.device("cuda", device)
         self._pending = {}
+        if operator_budget is not None:
+            _raise(load().bfm_server_operator_budget(self.handle, int(operator_budget)))
 
     def close(self):
         if self.handle:
@@ -391,13 +416,13 @@ class Server:
 
     def request(self, Y, *, n, order=3, freq=23.0, h=0.25, h_window=0, lam=2.5,
                 mask_mode=MASK_NONE, valid=None, times=None, outputs=("brk", "mag"),
-                out_dtype=torch.float64):
+                out_dtype=torch.float64, precision="fp64"):
         """The bfm_request for these arguments (no device work).  The request
         keeps its observation times alive."""
         if Y.dtype not in _Y_DTYPES or Y.device.type != "cuda":
             raise ValueError("Y must be a float32, bfloat16 or float16 tensor on a HIP device")
         Y, N, P, ld = _series_layout(Y)
-        prm = make_params(N, n, order, freq, h, h_window, lam, mask_mode, times)
+        prm = make_params(N, n, order, freq, h, h_window, lam, mask_mode, times, precision)
         want = 0
         for name in outputs:
             if name != "brk":

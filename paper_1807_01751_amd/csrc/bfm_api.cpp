@@ -15,17 +15,38 @@
 
 #include "bfm_internal.hpp"
 
+// Device memory of one cached operator block: a range of the context's
+// arena (or, for a block larger than the whole arena, its own allocation), the
+// event recorded after the last launch that reads it, and its last-use stamp.
+struct OpBlock {
+    size_t off = 0, bytes = 0;
+    char* own = nullptr;
+    hipEvent_t last = nullptr;
+    uint64_t stamp = 0;
+};
+
 struct bfm_ctx {
     int device = 0;
     size_t max_lds = 0;  // dynamic LDS bytes one workgroup may use
     int cus = 0;         // compute units
     std::mutex mu;
+    // Operator cache: one device arena of op_budget bytes, allocated at the
+    // first parameter set and carved first-fit; least recently used blocks are
+    // evicted when a new one does not fit, each after its own last launch has
+    // finished (no device-wide synchronisation).
+    size_t op_budget = (size_t)64 << 20;
+    char* arena = nullptr;
+    std::map<size_t, size_t> arena_free;  // offset -> length
+    uint64_t clock = 0;
+    int64_t evictions = 0;
+    size_t cached_bytes = 0;
     struct Entry {
         bfm::PlainOps ops;
         double* dev = nullptr;  // q | w | bnd | bmap
         bfm::PeriodicOps per;   // per.F == 0: the period-blocked kernel does not apply
         double* pdev = nullptr; // rt | ri | hh | wh | bnd
         std::vector<double> times;  // observation times the operators were built for
+        OpBlock blk;
     };
     // (N, n, k, h_window, f, h_frac, lambda, hash of the observation times or 0)
     using Key = std::tuple<int, int, int, int, double, double, double, uint64_t>;
@@ -38,6 +59,7 @@ struct bfm_ctx {
         bfm::MaskedOps ops;
         double* dev = nullptr;  // x | g | ph
         std::vector<double> times;
+        OpBlock blk;
     };
     std::map<Key, MEntry> masked;
 };
@@ -87,7 +109,7 @@ int check(const bfm_params* prm, int64_t P, int64_t ld)
         for (int t = 0; t < p.n_obs; ++t)
             if (!std::isfinite(p.times[t]) || (t > 0 && !(p.times[t] > p.times[t - 1])))
                 return fail(BFM_E_INVAL, "times must be finite and strictly increasing (index %d)", t);
-    if (p.precision != BFM_PREC_FP64)
+    if (p.precision != BFM_PREC_FP64 && p.precision != BFM_PREC_FP32)
         return fail(BFM_E_INVAL, "unknown precision %d", p.precision);
     if (P < 0) return fail(BFM_E_INVAL, "P must be >= 0");
     if (P > ((int64_t)1 << 30)) return fail(BFM_E_INVAL, "P must be <= 2^30 per call");
@@ -156,21 +178,138 @@ std::vector<double> times_of(const bfm_params& p)
     return p.times ? std::vector<double>(p.times, p.times + p.n_obs) : std::vector<double>();
 }
 
+constexpr size_t kBlockAlign = 256;
+size_t align_up(size_t n) { return (n + kBlockAlign - 1) / kBlockAlign * kBlockAlign; }
+
+// Returns a block's memory once its last launch has finished (a wait on that
+// block's event only: launches on other streams go on).  Call with ctx->mu held.
+void block_free(bfm_ctx* ctx, OpBlock& b)
+{
+    if (b.last) {
+        (void)hipEventSynchronize(b.last);
+        (void)hipEventDestroy(b.last);
+    }
+    if (b.own) {
+        (void)hipFree(b.own);
+    } else if (b.bytes) {
+        auto it = ctx->arena_free.emplace(b.off, b.bytes).first;
+        auto next = std::next(it);
+        if (next != ctx->arena_free.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            ctx->arena_free.erase(next);
+        }
+        if (it != ctx->arena_free.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                ctx->arena_free.erase(it);
+            }
+        }
+    }
+    ctx->cached_bytes -= b.bytes;
+    b = OpBlock{};
+}
+
+bool block_idle(const OpBlock& b) { return !b.last || hipEventQuery(b.last) == hipSuccess; }
+
+// Evicts the least recently used cached entry (only an idle one if
+// idle_only).  Returns false if there was none to evict.
+bool evict_lru(bfm_ctx* ctx, bool idle_only)
+{
+    uint64_t best = UINT64_MAX;
+    int which = -1;
+    bfm_ctx::Key key;
+    for (auto& kv : ctx->plain)
+        if (kv.second.blk.stamp < best && (!idle_only || block_idle(kv.second.blk))) {
+            best = kv.second.blk.stamp;
+            which = 0;
+            key = kv.first;
+        }
+    for (auto& kv : ctx->masked)
+        if (kv.second.blk.stamp < best && (!idle_only || block_idle(kv.second.blk))) {
+            best = kv.second.blk.stamp;
+            which = 1;
+            key = kv.first;
+        }
+    if (which < 0) return false;
+    if (which == 0) {
+        auto it = ctx->plain.find(key);
+        block_free(ctx, it->second.blk);
+        ctx->plain.erase(it);
+    } else {
+        auto it = ctx->masked.find(key);
+        block_free(ctx, it->second.blk);
+        ctx->masked.erase(it);
+    }
+    ++ctx->evictions;
+    return true;
+}
+
+// Device memory for a new operator block of `bytes`, evicting least recently
+// used blocks (idle ones first) while it does not fit.  Call with ctx->mu held.
+int block_get(bfm_ctx* ctx, size_t bytes, OpBlock* b, char** base)
+{
+    const size_t n = align_up(bytes);
+    *b = OpBlock{};
+    hipError_t e;
+    if (!ctx->arena && ctx->op_budget > 0) {
+        e = hipMalloc(&ctx->arena, ctx->op_budget);
+        if (e != hipSuccess) {
+            ctx->arena = nullptr;
+            return hip_fail(e, "hipMalloc(operator arena)");
+        }
+        ctx->arena_free[0] = ctx->op_budget;
+    }
+    if (n > ctx->op_budget) {  // larger than the whole arena: a block of its own
+        e = hipMalloc(&b->own, n);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(operators)");
+        *base = b->own;
+    } else {
+        for (;;) {
+            auto it = std::find_if(ctx->arena_free.begin(), ctx->arena_free.end(),
+                                   [&](const std::pair<const size_t, size_t>& f) { return f.second >= n; });
+            if (it != ctx->arena_free.end()) {
+                b->off = it->first;
+                const size_t rest = it->second - n, at = it->first + n;
+                ctx->arena_free.erase(it);
+                if (rest) ctx->arena_free[at] = rest;
+                break;
+            }
+            if (!evict_lru(ctx, true) && !evict_lru(ctx, false))
+                return fail(BFM_E_NOMEM, "operator block of %zu B does not fit the %zu B budget", n,
+                            ctx->op_budget);
+        }
+        *base = ctx->arena + b->off;
+    }
+    b->bytes = n;
+    ctx->cached_bytes += n;
+    e = hipEventCreateWithFlags(&b->last, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        block_free(ctx, *b);
+        return hip_fail(e, "hipEventCreate(operators)");
+    }
+    return BFM_SUCCESS;
+}
+
+// Marks a block as read by the launch just enqueued on `s`.
+void block_used(bfm_ctx* ctx, OpBlock& b, hipStream_t s)
+{
+    b.stamp = ++ctx->clock;
+    (void)hipEventRecord(b.last, s);
+}
+
 // A cached entry built for other observation times under the same hash is
-// dropped (its device block freed) so that it is rebuilt.
+// dropped (its block returned once its last launch has finished) so that it
+// is rebuilt.
 template <typename Map>
-void drop_if_stale(Map& m, const bfm_ctx::Key& key, const bfm_params& p)
+void drop_if_stale(bfm_ctx* ctx, Map& m, const bfm_ctx::Key& key, const bfm_params& p)
 {
     auto it = m.find(key);
     if (it == m.end() || !p.times) return;
     if (it->second.times.size() == (size_t)p.n_obs &&
         std::memcmp(it->second.times.data(), p.times, (size_t)p.n_obs * sizeof(double)) == 0)
         return;
-    // Kernels launched earlier with this block may still run on some stream.
-    (void)hipDeviceSynchronize();
-    (void)hipFree(it->second.dev);
-    if constexpr (std::is_same_v<typename Map::mapped_type, bfm_ctx::Entry>)
-        if (it->second.pdev) (void)hipFree(it->second.pdev);
+    block_free(ctx, it->second.blk);
     m.erase(it);
 }
 
@@ -179,46 +318,40 @@ void drop_if_stale(Map& m, const bfm_ctx::Key& key, const bfm_params& p)
 int plain_entry(bfm_ctx* ctx, const bfm_params& p, bfm_ctx::Entry** out)
 {
     bfm_ctx::Key key{p.n_obs, p.n_hist, p.order, p.h_window, p.freq, p.h_frac, p.lambda, times_hash(p)};
-    drop_if_stale(ctx->plain, key, p);
+    drop_if_stale(ctx, ctx->plain, key, p);
     auto it = ctx->plain.find(key);
     if (it == ctx->plain.end()) {
         bfm_ctx::Entry ent;
         ent.times = times_of(p);
         bfm::build_plain_ops(p, &ent.ops);
-        const size_t nq = ent.ops.q.size(), nw = ent.ops.w.size(), nb = ent.ops.bnd.size(),
-                     nm = ent.ops.bmap.size();
+        // One block: q | w | bnd | bmap, then (period-blocked kernel) rt | ri | hh | wh | bnd.
         std::vector<double> host;
-        host.reserve(nq + nw + nb + nm);
         host.insert(host.end(), ent.ops.q.begin(), ent.ops.q.end());
         host.insert(host.end(), ent.ops.w.begin(), ent.ops.w.end());
         host.insert(host.end(), ent.ops.bnd.begin(), ent.ops.bnd.end());
         host.insert(host.end(), ent.ops.bmap.begin(), ent.ops.bmap.end());
-        hipError_t e = hipMalloc(&ent.dev, host.size() * sizeof(double));
-        if (e != hipSuccess) return hip_fail(e, "hipMalloc(operators)");
-        // A synchronous copy: the operator block is a few tens of KB and this
-        // happens once per parameter set.
-        e = hipMemcpy(ent.dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            (void)hipFree(ent.dev);
-            return hip_fail(e, "hipMemcpy(operators)");
-        }
+        const size_t nplain = host.size();
         const int F = bfm::periodic_period(p, ent.ops);
         if (F > 0) {
             bfm::build_periodic_ops(p, ent.ops, F, &ent.per);
-            std::vector<double> ph(ent.per.rt);
-            ph.insert(ph.end(), ent.per.ri.begin(), ent.per.ri.end());
-            ph.insert(ph.end(), ent.per.hh.begin(), ent.per.hh.end());
-            ph.insert(ph.end(), ent.per.wh.begin(), ent.per.wh.end());
-            ph.insert(ph.end(), ent.ops.bnd.begin(), ent.ops.bnd.end());
-            e = hipMalloc(&ent.pdev, ph.size() * sizeof(double));
-            if (e == hipSuccess)
-                e = hipMemcpy(ent.pdev, ph.data(), ph.size() * sizeof(double), hipMemcpyHostToDevice);
-            if (e != hipSuccess) {
-                (void)hipFree(ent.dev);
-                if (ent.pdev) (void)hipFree(ent.pdev);
-                return hip_fail(e, "periodic operators");
-            }
+            host.insert(host.end(), ent.per.rt.begin(), ent.per.rt.end());
+            host.insert(host.end(), ent.per.ri.begin(), ent.per.ri.end());
+            host.insert(host.end(), ent.per.hh.begin(), ent.per.hh.end());
+            host.insert(host.end(), ent.per.wh.begin(), ent.per.wh.end());
+            host.insert(host.end(), ent.ops.bnd.begin(), ent.ops.bnd.end());
         }
+        char* base = nullptr;
+        int rc = block_get(ctx, host.size() * sizeof(double), &ent.blk, &base);
+        if (rc) return rc;
+        // A synchronous copy: the operator block is a few tens of KB and this
+        // happens once per parameter set.
+        hipError_t e = hipMemcpy(base, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            block_free(ctx, ent.blk);
+            return hip_fail(e, "hipMemcpy(operators)");
+        }
+        ent.dev = reinterpret_cast<double*>(base);
+        ent.pdev = F > 0 ? ent.dev + nplain : nullptr;
         it = ctx->plain.emplace(key, std::move(ent)).first;
     }
     *out = &it->second;
@@ -230,7 +363,7 @@ int fit_masked(bfm_ctx* ctx, const bfm_params& p, const void* Y, int y_dtype, in
                const uint8_t* valid, int64_t ldv, const bfm_outputs& out, hipStream_t s)
 {
     bfm_ctx::Key key{p.n_obs, p.n_hist, p.order, p.h_window, p.freq, p.h_frac, 0.0, times_hash(p)};
-    drop_if_stale(ctx->masked, key, p);
+    drop_if_stale(ctx, ctx->masked, key, p);
     auto it = ctx->masked.find(key);
     if (it == ctx->masked.end()) {
         bfm_ctx::MEntry ent;
@@ -239,13 +372,15 @@ int fit_masked(bfm_ctx* ctx, const bfm_params& p, const void* Y, int y_dtype, in
         std::vector<double> host(ent.ops.x);
         host.insert(host.end(), ent.ops.g.begin(), ent.ops.g.end());
         host.insert(host.end(), ent.ops.ph.begin(), ent.ops.ph.end());
-        hipError_t e = hipMalloc(&ent.dev, host.size() * sizeof(double));
-        if (e != hipSuccess) return hip_fail(e, "hipMalloc(masked operators)");
-        e = hipMemcpy(ent.dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
+        char* base = nullptr;
+        int rc = block_get(ctx, host.size() * sizeof(double), &ent.blk, &base);
+        if (rc) return rc;
+        hipError_t e = hipMemcpy(base, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
-            (void)hipFree(ent.dev);
+            block_free(ctx, ent.blk);
             return hip_fail(e, "hipMemcpy(masked operators)");
         }
+        ent.dev = reinterpret_cast<double*>(base);
         it = ctx->masked.emplace(key, std::move(ent)).first;
     }
     const bfm::MaskedOps& ops = it->second.ops;
@@ -271,6 +406,7 @@ int fit_masked(bfm_ctx* ctx, const bfm_params& p, const void* Y, int y_dtype, in
     a.g = it->second.dev + ops.x.size();
     a.ph = a.g + ops.g.size();
     a.F = ops.F;
+    a.m32 = p.precision == BFM_PREC_FP32;
     a.N = p.n_obs;
     a.n = p.n_hist;
     a.h_window = p.h_window;
@@ -290,12 +426,80 @@ int fit_masked(bfm_ctx* ctx, const bfm_params& p, const void* Y, int y_dtype, in
     hipError_t e = blocked ? bfm::launch_masked_periodic(a, p.order, p.mask_mode, s)
                            : bfm::launch_masked(a, p.order, p.mask_mode, s);
     if (e != hipSuccess) return hip_fail(e, "masked kernel launch");
+    block_used(ctx, it->second.blk, s);
     return BFM_SUCCESS;
 }
 
 }  // namespace
 
+namespace bfm {
+
+size_t operator_block_bound(const bfm_params& p)
+{
+    const size_t N = (size_t)p.n_obs, n = (size_t)p.n_hist, k = (size_t)p.order, np = 2 + 2 * k;
+    const size_t M = N > n ? N - n : 0;
+    int F = 0;
+    for (int f : kPeriods)
+        if (!p.times && p.freq == (double)f) F = f;
+    size_t doubles;
+    if (p.mask_mode == BFM_MASK_NAN || p.mask_mode == BFM_MASK_EXPLICIT) {
+        const bool blocked = F > 0 && p.order <= kMaskedMaxOrder && p.n_hist <= kMaskedPeriodicMaxHist;
+        doubles = N * np + n * (2 + 6 * k) + (blocked ? (size_t)F * 4 * k : 0);
+    } else {
+        doubles = N * np + M * np + M + np * np;
+        if (F > 0 && p.order <= kPeriodicMaxOrder && window_length(p, p.n_hist) >= F)
+            doubles += 2 * np * np + 2 * (size_t)F * 2 * k + M;
+    }
+    return align_up(doubles * sizeof(double));
+}
+
+bool operator_room(bfm_ctx* ctx, const bfm_params& p)
+{
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    const bool masked = p.mask_mode == BFM_MASK_NAN || p.mask_mode == BFM_MASK_EXPLICIT;
+    const bfm_ctx::Key key{p.n_obs, p.n_hist, p.order, p.h_window, p.freq, p.h_frac,
+                           masked ? 0.0 : p.lambda, times_hash(p)};
+    if (masked ? ctx->masked.count(key) != 0 : ctx->plain.count(key) != 0) return true;
+    const size_t need = operator_block_bound(p);
+    if (need > ctx->op_budget) return true;  // a block of its own
+    size_t busy = 0;
+    for (auto& kv : ctx->plain)
+        if (!block_idle(kv.second.blk)) busy += kv.second.blk.bytes;
+    for (auto& kv : ctx->masked)
+        if (!block_idle(kv.second.blk)) busy += kv.second.blk.bytes;
+    return need + busy <= ctx->op_budget;
+}
+
+size_t operator_budget_of(bfm_ctx* ctx)
+{
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    return ctx->op_budget;
+}
+
+}  // namespace bfm
+
 extern "C" {
+
+int bfm_operator_budget(bfm_ctx* ctx, size_t bytes)
+{
+    if (!ctx) return fail(BFM_E_INVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (ctx->arena || !ctx->plain.empty() || !ctx->masked.empty())
+        return fail(BFM_E_INVAL, "the operator budget is set before the first call on the context");
+    ctx->op_budget = align_up(bytes);
+    return BFM_SUCCESS;
+}
+
+int bfm_cache_get_stats(bfm_ctx* ctx, bfm_cache_stats* st)
+{
+    if (!ctx || !st) return fail(BFM_E_INVAL, "ctx and st are required");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    st->entries = (int64_t)(ctx->plain.size() + ctx->masked.size());
+    st->bytes = (int64_t)ctx->cached_bytes;
+    st->budget = (int64_t)ctx->op_budget;
+    st->evictions = ctx->evictions;
+    return BFM_SUCCESS;
+}
 
 int bfm_version(void) { return BFM_VERSION; }
 
@@ -339,12 +543,10 @@ int bfm_destroy(bfm_ctx* ctx)
     if (!ctx) return BFM_SUCCESS;
     {
         DeviceGuard g(ctx->device);
-        for (auto& kv : ctx->plain) {
-            if (kv.second.dev) (void)hipFree(kv.second.dev);
-            if (kv.second.pdev) (void)hipFree(kv.second.pdev);
-        }
-        for (auto& kv : ctx->masked)
-            if (kv.second.dev) (void)hipFree(kv.second.dev);
+        std::lock_guard<std::mutex> lock(ctx->mu);
+        for (auto& kv : ctx->plain) block_free(ctx, kv.second.blk);
+        for (auto& kv : ctx->masked) block_free(ctx, kv.second.blk);
+        if (ctx->arena) (void)hipFree(ctx->arena);
     }
     delete ctx;
     return BFM_SUCCESS;
@@ -445,6 +647,7 @@ int bfm_fit_monitor_typed(bfm_ctx* ctx, const bfm_params* prm, const void* Y, in
                                     p.mask_mode, valid, ldv, s);
         return e == hipSuccess ? BFM_SUCCESS : hip_fail(e, "fill_status launch");
     }
+    ent->blk.stamp = ++ctx->clock;
     const size_t lds = (size_t)ops.H * bfm::kPlainBlock * sizeof(float);
     if (lds > ctx->max_lds)
         return fail(BFM_E_UNSUPPORTED, "window H=%d needs %zu B of LDS per workgroup (max %zu)",
@@ -481,6 +684,7 @@ int bfm_fit_monitor_typed(bfm_ctx* ctx, const bfm_params* prm, const void* Y, in
         a.out_f64 = out->out_dtype == BFM_OUT_F64;
         e = bfm::launch_periodic(a, p.order, ent->per.F, s);
         if (e != hipSuccess) return hip_fail(e, "periodic kernel launch");
+        block_used(ctx, ent->blk, s);
         return BFM_SUCCESS;
     }
     if (narrow)
@@ -515,6 +719,7 @@ int bfm_fit_monitor_typed(bfm_ctx* ctx, const bfm_params* prm, const void* Y, in
     a.out_f64 = out->out_dtype == BFM_OUT_F64;
     e = bfm::launch_plain(a, np, s);
     if (e != hipSuccess) return hip_fail(e, "plain kernel launch");
+    block_used(ctx, ent->blk, s);
     return BFM_SUCCESS;
 }
 

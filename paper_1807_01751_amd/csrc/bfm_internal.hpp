@@ -167,6 +167,7 @@ struct MaskedArgs {
     const double* g;       // n x ng
     const double* ph;      // F x 4k (period-blocked kernel)
     int F;                 // 0: general kernel
+    int m32;               // BFM_PREC_FP32: the period-blocked kernel's MOSUM in FP32
     int N, n, h_window, cap;
     double h_frac, lambda;
     double tc, ts;         // time centre and scale of the trend column: tau = (t - tc) / ts
@@ -184,6 +185,8 @@ hipError_t launch_masked(const MaskedArgs& a, int order, int mask_mode, hipStrea
 hipError_t launch_masked_periodic(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
 hipError_t launch_masked_periodic_bf16(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
 hipError_t launch_masked_periodic_f16(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
+hipError_t launch_masked_periodic_m32(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
+hipError_t launch_masked_periodic_m32_f16(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
 size_t masked_periodic_lds_bytes(int cap);
 size_t masked_lds_bytes(int cap);
 
@@ -200,6 +203,14 @@ hipError_t select_rank(const double* v, int64_t cnt, int64_t rank, uint32_t* cou
 // noalloc_scratch returns the kept address (nullptr before the lookup).
 hipError_t noalloc_scratch_init(int device);
 void* noalloc_scratch(int device);
+
+// Operator cache of a context, as the serving runtime sees it: an upper bound
+// on the device bytes of a parameter set's operator block (256-byte aligned),
+// whether that block is cached or would fit next to the blocks still read by
+// unfinished launches, and the context's budget.
+size_t operator_block_bound(const bfm_params& p);
+bool operator_room(bfm_ctx* ctx, const bfm_params& p);
+size_t operator_budget_of(bfm_ctx* ctx);
 
 // Every pixel gets `st` (or NONFINITE if one of its used observations is not
 // finite), brk = -1 and NaN floating outputs: used when the parameters make

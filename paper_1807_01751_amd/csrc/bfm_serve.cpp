@@ -112,6 +112,7 @@ struct Req {
     Layout lay;
     size_t off = 0;
     enum State { QUEUED, RUNNING, DONE } st = QUEUED;
+    bool waited_ops = false;  // held at the head of the queue for operator room
     Clock::time_point t_submit, t_admit, t_done;
     bfm_result res{};
 };
@@ -141,8 +142,9 @@ struct bfm_server {
     std::thread worker;
     bool stop = false;
     uint64_t next_id = 1;
-    int64_t running = 0, max_running = 0, completed = 0;
+    int64_t running = 0, max_running = 0, completed = 0, operator_waits = 0;
     size_t in_use = 0;
+    bool submitted = false;  // the operator budget is fixed from the first request on
 };
 
 namespace {
@@ -224,6 +226,14 @@ void worker_loop(bfm_server* s)
                                           [](const bfm_server::SlotState& x) { return !x.req; });
             if (free_slot == s->slots.end()) break;
             Req* q = s->queue.front();
+            // HBM footprint: the operators of a parameter set not yet cached
+            // must fit next to those that running requests read, and the
+            // outputs in the pool.
+            if (q->r.P > 0 && !bfm::operator_room(s->ctx, q->r.prm)) {
+                if (!q->waited_ops) ++s->operator_waits;
+                q->waited_ops = true;
+                break;
+            }
             if (!s->pool.alloc(q->lay.total, &q->off)) break;
             s->queue.pop_front();
             s->in_use += q->lay.total;
@@ -338,10 +348,12 @@ int bfm_server_submit(bfm_server* s, const bfm_request* req, uint64_t* ticket)
     q->r = *req;
     layout_of(q->r, &q->lay);
     if (q->lay.total > s->pool_bytes) return BFM_E_NOMEM;
+    if (bfm::operator_block_bound(q->r.prm) > bfm::operator_budget_of(s->ctx)) return BFM_E_NOMEM;
     q->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) return BFM_E_INVAL;
+        s->submitted = true;
         q->id = s->next_id++;
         *ticket = q->id;
         s->queue.push_back(q.get());
@@ -429,13 +441,28 @@ int bfm_server_take(bfm_server* s, uint64_t ticket, const bfm_outputs* dst, void
 int bfm_server_get_stats(bfm_server* s, bfm_server_stats* st)
 {
     if (!s || !st) return BFM_E_INVAL;
+    bfm_cache_stats cs{};
+    int rc = bfm_cache_get_stats(s->ctx, &cs);
+    if (rc) return rc;
     std::lock_guard<std::mutex> lk(s->mu);
     st->queued = (int64_t)s->queue.size();
     st->running = s->running;
     st->completed = s->completed;
     st->pool_in_use = (int64_t)s->in_use;
     st->max_running = s->max_running;
+    st->operator_entries = cs.entries;
+    st->operator_bytes = cs.bytes;
+    st->operator_evictions = cs.evictions;
+    st->operator_waits = s->operator_waits;
     return BFM_SUCCESS;
+}
+
+int bfm_server_operator_budget(bfm_server* s, size_t bytes)
+{
+    if (!s) return BFM_E_INVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->submitted) return BFM_E_INVAL;
+    return bfm_operator_budget(s->ctx, bytes);
 }
 
 int bfm_server_destroy(bfm_server* s)

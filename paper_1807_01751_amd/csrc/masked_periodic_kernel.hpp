@@ -15,7 +15,9 @@
 // The series may be stored as float32, BF16 or FP16 (template parameter T); the
 // arithmetic is the same.  This header holds the kernel template;
 // masked_periodic_kernel.hip (float32), masked_periodic_kernel_bf16.hip and
-// masked_periodic_kernel_f16.hip instantiate it.
+// masked_periodic_kernel_f16.hip instantiate it, and
+// masked_periodic_kernel_m32.hip / masked_periodic_kernel_m32_f16.hip its FP32
+// MOSUM form (BFM_PREC_FP32).
 //
 // One lane owns one pixel and streams its series once, time-major, in blocks
 // of F rows aligned to multiples of F, so a row's phase is a compile-time
@@ -34,6 +36,7 @@
 
 #include <climits>
 #include <cmath>
+#include <type_traits>
 
 #include "bfm_internal.hpp"
 #include "device_common.hpp"
@@ -65,6 +68,18 @@ __device__ __forceinline__ double min_num(double a, double b)
 {
     double r;
     asm volatile("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float max_num(float a, float b)
+{
+    float r;
+    asm volatile("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float min_num(float a, float b)
+{
+    float r;
+    asm volatile("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
     return r;
 }
 
@@ -205,10 +220,17 @@ struct CursorOf<true, T> {
 
 // LDS is what limits residency (one ring slot per window position and lane),
 // so the kernel may use up to 256 VGPRs without losing waves.
-template <int K, int F, bool EXPORT, bool EXPLICIT, typename T>
+//
+// M32 (BFM_PREC_FP32): the MOSUM in FP32.  The fit, sigma and each residual are
+// computed in FP64 as above; the residual is then rounded to float, kept in the
+// ring's 32-bit word (no 16-bit word: one LDS write and one read per row), and
+// the window sum, its extremes and the boundary test run in FP32 (the paper's
+// own MOSUM kernel computes in float).
+template <int K, int F, bool EXPORT, bool EXPLICIT, typename T, bool M32>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void
 masked_periodic_kernel(MaskedArgs a)
 {
+    using Acc = typename std::conditional<M32, float, double>::type;  // MOSUM arithmetic
     using Gk = Gram<K>;
     using Cur = CursorOf<EXPLICIT, T>;
     using V = typename Cur::type::value_type;
@@ -452,7 +474,7 @@ masked_periodic_kernel(MaskedArgs a)
     // ---- the last H observed history values become residuals ----
     // Four slots per step, so that their phase-table gathers are in flight
     // together; the wave stops at its largest window.
-    double S = 0.0;
+    Acc S = 0;
     int hmax = monitor ? H : 0;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) hmax = max(hmax, __shfl_xor(hmax, o));
@@ -484,7 +506,13 @@ masked_periodic_kernel(MaskedArgs a)
                     pr = fma(beta[2 * j], hr[k][2 * (j - 1)], pr);
                     pr = fma(beta[2 * j + 1], hr[k][2 * (j - 1) + 1], pr);
                 }
-                S += ring_store(rhi, rmid, slot[k], (double)y[k] - pr);
+                if constexpr (M32) {
+                    const float rf = (float)((double)y[k] - pr);
+                    rhi[slot[k] * kBlock] = __float_as_uint(rf);
+                    S += rf;
+                } else {
+                    S += ring_store(rhi, rmid, slot[k], (double)y[k] - pr);
+                }
             }
         }
     }
@@ -507,7 +535,8 @@ masked_periodic_kernel(MaskedArgs a)
     room = __builtin_amdgcn_readfirstlane(room);  // the same in every lane: keep it scalar
     const int t_split = room >= N - n ? N : n + (room > 0 ? room : 0);
     int u1 = nv;  // compacted (1-based) position of the latest observation
-    double hi = -INFINITY, lo = INFINITY;
+    Acc hi = -INFINITY, lo = INFINITY;
+    const Acc thr_acc = (Acc)thr_flat;
     int brk = INT_MAX;
     double Gb = 0.0;
     const double rscale = 1.0 / scale;
@@ -516,7 +545,7 @@ masked_periodic_kernel(MaskedArgs a)
     // previous write, so the window still holds exactly the last H residuals):
     // its LDS latency overlaps the rest of the row.
     uint32_t old_hi = rhi[rp * kBlock];
-    uint16_t old_mid = rmid[rp * kBlock];
+    uint16_t old_mid = M32 ? 0 : rmid[rp * kBlock];
     stream_blocks<F>(
         [&](int t) { return Cur::at(a, t, lane); }, n, N,
         [&](int u, int t, V val, bool in) {
@@ -524,22 +553,28 @@ masked_periodic_kernel(MaskedArgs a)
             const float v = value(val);
             if (EXPLICIT) bad = bad || (ok && !isfinite(v));
             if (ok) {  // lanes whose row is missing sit this one out
-                const double r = ring_store(rhi, rmid, wp, (double)v - (Pw[u] + Gb));
-                S += r - ring_value(old_hi, old_mid);
+                if constexpr (M32) {
+                    const float r = (float)((double)v - (Pw[u] + Gb));
+                    rhi[wp * kBlock] = __float_as_uint(r);
+                    S += r - __uint_as_float(old_hi);
+                } else {
+                    const double r = ring_store(rhi, rmid, wp, (double)v - (Pw[u] + Gb));
+                    S += r - ring_value(old_hi, old_mid);
+                }
                 wp = wp + 1 == cap ? 0 : wp + 1;
                 rp = rp + 1 == cap ? 0 : rp + 1;
                 old_hi = rhi[rp * kBlock];
-                old_mid = rmid[rp * kBlock];
+                if (!M32) old_mid = rmid[rp * kBlock];
                 hi = max_num(hi, S);
                 lo = min_num(lo, S);
                 ++u1;
-                bool cross = fabs(S) > thr_flat;
+                bool cross = fabs(S) > thr_acc;
                 if (t >= t_split)  // wave-uniform; not reached while every u/n_v stays below e
-                    cross = cross_past_e(cross, S, thr2, u1, ue, nv, l2nv);
+                    cross = cross_past_e(cross, (double)S, thr2, u1, ue, nv, l2nv);
                 brk = cross ? min(brk, t - n) : brk;
             }
             if (EXPORT && a.mosum && active && in)
-                put_out(a.mosum, (int64_t)(t - n) * a.P + lane, monitor && ok ? S * rscale : qnan,
+                put_out(a.mosum, (int64_t)(t - n) * a.P + lane, monitor && ok ? (double)S * rscale : qnan,
                         a.out_f64);
         },
         pre, [](const V*) {});
@@ -550,7 +585,7 @@ masked_periodic_kernel(MaskedArgs a)
 
     const bool have_fit = fitted && st != BFM_ST_NONFINITE;
     double mag = qnan;
-    if (st == BFM_ST_OK) mag = (hi >= -lo ? hi : lo) * rscale;
+    if (st == BFM_ST_OK) mag = (double)(hi >= -lo ? hi : lo) * rscale;
     if (st != BFM_ST_OK || brk == INT_MAX) brk = -1;
     a.brk[pix] = brk;
     if (a.mag) put_out(a.mag, pix, mag, a.out_f64);
@@ -577,50 +612,50 @@ masked_periodic_kernel(MaskedArgs a)
     }
 }
 
-template <int K, int F, bool EXPLICIT, typename T>
+template <int K, int F, bool EXPLICIT, typename T, bool M32>
 hipError_t launch_kf(const MaskedArgs& a, hipStream_t stream)
 {
     const dim3 grid((unsigned)((a.P + kBlock - 1) / kBlock));
     const size_t lds = (size_t)ring_slots(a.cap) * kBlock * 6;
     if (a.n >= 65536) return hipErrorInvalidValue;  // history rows are kept as 16-bit indices
     if (a.resid || a.mosum)
-        hipLaunchKernelGGL((masked_periodic_kernel<K, F, true, EXPLICIT, T>), grid, dim3(kBlock), lds,
+        hipLaunchKernelGGL((masked_periodic_kernel<K, F, true, EXPLICIT, T, M32>), grid, dim3(kBlock), lds,
                            stream, a);
     else
-        hipLaunchKernelGGL((masked_periodic_kernel<K, F, false, EXPLICIT, T>), grid, dim3(kBlock), lds,
+        hipLaunchKernelGGL((masked_periodic_kernel<K, F, false, EXPLICIT, T, M32>), grid, dim3(kBlock), lds,
                            stream, a);
     return hipGetLastError();
 }
 
-template <int K, bool EXPLICIT, typename T>
+template <int K, bool EXPLICIT, typename T, bool M32>
 hipError_t launch_k(const MaskedArgs& a, hipStream_t stream)
 {
     switch (a.F) {
-    case 12: return launch_kf<K, 12, EXPLICIT, T>(a, stream);
-    case 23: return launch_kf<K, 23, EXPLICIT, T>(a, stream);
-    case 24: return launch_kf<K, 24, EXPLICIT, T>(a, stream);
+    case 12: return launch_kf<K, 12, EXPLICIT, T, M32>(a, stream);
+    case 23: return launch_kf<K, 23, EXPLICIT, T, M32>(a, stream);
+    case 24: return launch_kf<K, 24, EXPLICIT, T, M32>(a, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <bool EXPLICIT, typename T>
+template <bool EXPLICIT, typename T, bool M32>
 hipError_t launch_mode(const MaskedArgs& a, int order, hipStream_t stream)
 {
     switch (order) {
-    case 0: return launch_k<0, EXPLICIT, T>(a, stream);
-    case 1: return launch_k<1, EXPLICIT, T>(a, stream);
-    case 2: return launch_k<2, EXPLICIT, T>(a, stream);
-    case 3: return launch_k<3, EXPLICIT, T>(a, stream);
-    case 4: return launch_k<4, EXPLICIT, T>(a, stream);
+    case 0: return launch_k<0, EXPLICIT, T, M32>(a, stream);
+    case 1: return launch_k<1, EXPLICIT, T, M32>(a, stream);
+    case 2: return launch_k<2, EXPLICIT, T, M32>(a, stream);
+    case 3: return launch_k<3, EXPLICIT, T, M32>(a, stream);
+    case 4: return launch_k<4, EXPLICIT, T, M32>(a, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <typename T>
+template <typename T, bool M32 = false>
 hipError_t launch_t(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream)
 {
-    return mask_mode == BFM_MASK_EXPLICIT ? launch_mode<true, T>(a, order, stream)
-                                          : launch_mode<false, T>(a, order, stream);
+    return mask_mode == BFM_MASK_EXPLICIT ? launch_mode<true, T, M32>(a, order, stream)
+                                          : launch_mode<false, T, M32>(a, order, stream);
 }
 
 }  // namespace

@@ -202,6 +202,19 @@ def test_server_create_without_device_reports_nodevice(bfm):
     assert lib.bfm_server_destroy(None) == 0
 
 
+def test_operator_cache_entry_points_reject_without_device(bfm):
+    """The operator-cache entry points check their arguments without a device."""
+    lib = ctypes.CDLL(bfm.LIB_PATH)
+    lib.bfm_operator_budget.argtypes = [ctypes.c_void_p, ctypes.c_size_t]
+    lib.bfm_cache_get_stats.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.bfm_server_operator_budget.argtypes = [ctypes.c_void_p, ctypes.c_size_t]
+    st = bfm.CacheStats()
+    assert lib.bfm_operator_budget(None, 1 << 20) == bfm.E_INVAL
+    assert lib.bfm_cache_get_stats(None, ctypes.byref(st)) == bfm.E_INVAL
+    assert lib.bfm_server_operator_budget(None, 1 << 20) == bfm.E_INVAL
+    assert _struct_fields("bfm_cache_stats") == [f[0] for f in bfm.CacheStats._fields_]
+
+
 def test_simulated_lambda_entry_points_reject_without_device(bfm):
     """The critical-value entry points validate their arguments before any
     device work: a NULL context, bad parameters and bad alpha or path counts."""

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 import torch
 
-from parity import compare, to_numpy, used_history
+from parity import compare, margins, to_numpy, used_history
 
 pytestmark = pytest.mark.gpu
 
@@ -186,6 +186,27 @@ def test_config4_full_size_sampled(bfm, orc, order):
     o = orc.fit_monitor(Ys, n=n, order=order, mask_mode=orc.MASK_NAN, threads=0)
     rep = compare({k: v[idx] for k, v in a.items()}, o, lam=2.5, n_v=used_history(Ys, n))
     say(f"config 4 float32 order {order}: sample {rep}")
+    # The same tile with the MOSUM in FP32 (BFM_PREC_FP32), at the FP32 bar:
+    # sigma 1e-9 (FP64 fit), magnitude 1e-4 (its size where the extremes tie),
+    # break indices equal unless within 1e-3 of the boundary.
+    g32 = to_numpy(bfm.fit_monitor(Y, n=n, order=order, mask_mode=bfm.MASK_NAN, outputs=lean,
+                                   precision="fp32"))
+    g32 = {k: v[idx] for k, v in g32.items()}
+    ok = o["status"] == 0
+    np.testing.assert_array_equal(g32["status"], o["status"])
+    assert np.abs(g32["sigma"][ok] / o["sigma"][ok] - 1).max() <= 1e-9
+    hi, lo = np.nanmax(o["mosum"][:, ok], axis=0), np.nanmin(o["mosum"][:, ok], axis=0)
+    tie = np.abs(hi + lo) <= 2e-4 * np.maximum(hi, -lo)
+    gm, om = g32["mag"][ok], o["mag"][ok]
+    emag = np.where(tie, np.abs(np.abs(gm) - np.abs(om)), np.abs(gm - om)) / np.abs(om)
+    assert emag.max() <= 1e-4, emag.max()
+    diff = g32["brk"] != o["brk"]
+    if diff.any():
+        m = margins(o["mosum"][:, diff], g32["brk"][diff], o["brk"][diff], lam=2.5,
+                    n_v=used_history(Ys, n)[diff])
+        assert (m < 1e-3).all(), m
+    say(f"config 4 FP32 MOSUM order {order}: max rel mag {emag.max():.2e}, "
+        f"break mismatches {int(diff.sum())} (all marginal)")
     for dt in (torch.float16, torch.bfloat16):
         Yb = Y.to(dt)
         g = to_numpy(bfm.fit_monitor(Yb, n=n, order=order, mask_mode=bfm.MASK_NAN, outputs=lean))

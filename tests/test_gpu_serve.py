@@ -127,6 +127,54 @@ def test_admission_errors(bfm):
         assert srv.stats()["pool_in_use"] == 0
 
 
+def test_operator_budget_admission_and_eviction(bfm):
+    """Admission by HBM footprint: with an operator budget that holds one
+    parameter set's operator block, a request of another parameter set waits at
+    the head of the queue while the block is still read by a running launch
+    (four streams are free), the cache evicts the least recently used block
+    once its launch has finished, blocks are rebuilt when their parameter set
+    comes back, the cache never exceeds the budget, and every result equals the
+    same request run alone."""
+    import ctypes
+    shapes = [(1 << 19, N, 3, miss) for N in (240, 260, 280, 300) for miss in (0.0, 0.2)]
+    reqs = []
+    for i, (P, N, order, miss) in enumerate(shapes * 2):  # each parameter set twice
+        Y, n = payload(P, N, order, miss, 3000 + i % len(shapes))
+        reqs.append((Y, dict(n=n, order=order, mask_mode=1 if miss > 0 else 0,
+                             outputs=("brk", "mag", "sigma", "status"), out_dtype=torch.float64)))
+    say(f"case serve operator budget: {len(reqs)} requests, {len(shapes)} parameter sets")
+    alone = [to_numpy(bfm.fit_monitor(Y, **kw)) for Y, kw in reqs]
+    torch.cuda.synchronize()
+    sizes = []
+    for Y, kw in reqs:
+        nb = ctypes.c_size_t()
+        prm = bfm.make_params(Y.shape[0], kw["n"], kw["order"], mask_mode=kw["mask_mode"])
+        assert bfm.load().bfm_workspace_bytes(ctypes.byref(prm), Y.shape[1], ctypes.byref(nb)) == 0
+        sizes.append(nb.value)
+    budget = max(sizes) + 1024  # one block at a time
+    with bfm.Server(slots=4, pool_bytes=256 << 20, operator_budget=budget) as srv:
+        tickets = [srv.submit(Y, **kw) for Y, kw in reqs]
+        res = [srv.result(t) for t in tickets]
+        st = srv.stats()
+        with pytest.raises(bfm.BfmError) as e:  # fixed once requests were submitted
+            bfm._raise(bfm.load().bfm_server_operator_budget(srv.handle, 1 << 30))
+        assert e.value.code == bfm.E_INVAL
+    say("serve stats under an operator budget of", budget, st)
+    assert st["operator_waits"] > 0, "no request waited for operator room"
+    assert st["operator_bytes"] <= budget and st["operator_entries"] == 1
+    assert st["operator_evictions"] >= len(reqs) - 1
+    for i, (r, a) in enumerate(zip(res, alone)):
+        assert r["rc"] == 0, (i, r["rc"])
+        g = to_numpy({k: r[k] for k in a})
+        for k in a:
+            np.testing.assert_array_equal(g[k], a[k], err_msg=f"request {i} {k}")
+    with bfm.Server(slots=2, pool_bytes=64 << 20, operator_budget=1024) as srv:
+        Y, kw = reqs[0]
+        with pytest.raises(bfm.BfmError) as e:  # its operators exceed the whole budget
+            srv.submit(Y, **kw)
+        assert e.value.code == bfm.E_NOMEM
+
+
 def test_config5_largest_requests_in_the_mix(bfm, orc):
     """Requests at the serving workload's extremes (2048^2 and 256^2 pixels,
     N = 600 and 200, k = 10 and 6 regressors, up to 40% NaN, FP16 storage and a
