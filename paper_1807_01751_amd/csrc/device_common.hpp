@@ -72,6 +72,36 @@ __device__ __forceinline__ uint32_t load_flag(const uint8_t* row, uint32_t lane)
     return __builtin_amdgcn_raw_buffer_load_b8(row_rsrc(row), (int)lane, 0, kLoadNT);
 }
 
+// max and min of a running extreme and a value that is either a number or the
+// quiet NaN 0x7ff8... (every value here is the result of arithmetic): in IEEE
+// mode the hardware returns the other operand for a quiet NaN, so the
+// compiler's quieting of the loop-carried operand (one more instruction per
+// row) is not needed.
+__device__ __forceinline__ double max_num(double a, double b)
+{
+    double r;
+    asm volatile("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double min_num(double a, double b)
+{
+    double r;
+    asm volatile("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float max_num(float a, float b)
+{
+    float r;
+    asm volatile("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float min_num(float a, float b)
+{
+    float r;
+    asm volatile("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 template <typename T>
 __device__ __forceinline__ void put(void* base, int64_t idx, double v)
 {
@@ -257,12 +287,15 @@ __device__ __forceinline__ void stream_aligned(Cursor cur, int t0, int t1, Body&
         }
         cur.advance(hi - lo);
     };
+    // pre sees its range as compile-time constants for a whole block, so that
+    // per-row work in it becomes straight-line code there.
     auto run_block = [&](V* buf, int tb, int lo, int hi) {
-        pre(tb, lo, hi);
         if (lo == 0 && hi == F) {
+            pre(tb, 0, F);
 #pragma unroll
             for (int u = 0; u < F; ++u) body(u, tb + u, buf[u]);
         } else {
+            pre(tb, lo, hi);
 #pragma unroll
             for (int u = 0; u < F; ++u)
                 if (u >= lo && u < hi) body(u, tb + u, buf[u]);

@@ -55,33 +55,6 @@ constexpr int kBlock = 64;           // one wave per workgroup
 constexpr uint32_t kCountBits = 12;  // acc_r = W_r + (Q_r << 12)
 constexpr uint32_t kCountMask = (1u << kCountBits) - 1;
 
-// max and min of a running extreme and a value that is either a number or the
-// quiet NaN 0x7ff8...: in IEEE mode the hardware returns the other operand for a
-// quiet NaN, so the compiler's quieting of the operands is not needed.
-__device__ __forceinline__ double max_num(double a, double b)
-{
-    double r;
-    asm volatile("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-__device__ __forceinline__ double min_num(double a, double b)
-{
-    double r;
-    asm volatile("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-__device__ __forceinline__ float max_num(float a, float b)
-{
-    float r;
-    asm volatile("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-__device__ __forceinline__ float min_num(float a, float b)
-{
-    float r;
-    asm volatile("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
 
 // Boundary test of Eq. 4 past e for one lane: |S| > lambda scale sqrt(ln(u/n_v)),
 // squared: S^2 > thr2 ln(u/n_v).  Called only for rows where some lane of the
@@ -121,6 +94,8 @@ __device__ __forceinline__ double ring_value(uint32_t hi, uint16_t mid)
 
 __device__ __forceinline__ bool observed(float v) { return isfinite(v); }
 __device__ __forceinline__ bool observed(FlaggedObs o) { return o.ok != 0; }
+__device__ __forceinline__ float missing(float) { return __builtin_nanf(""); }
+__device__ __forceinline__ FlaggedObs missing(FlaggedObs o) { return {o.y, 0u}; }
 __device__ __forceinline__ float value(float v) { return v; }
 __device__ __forceinline__ float value(FlaggedObs o) { return o.y; }
 
@@ -128,8 +103,8 @@ __device__ __forceinline__ float value(FlaggedObs o) { return o.y; }
 // blocks ahead of the arithmetic in three register buffers used in turn (the
 // loads of a wave must cover the memory latency: the LDS ring limits how many
 // waves share a compute unit).  Every block runs the same unrolled code: a row
-// of the block outside [t0, t1) is passed with in = false (a masked-path body
-// treats it as missing), and its load reads the nearest row inside instead.
+// of the block outside [t0, t1) reads the nearest row inside, is replaced by a
+// missing value before the rows run, and is passed with in = false.
 // init(buf) sees the first block before any row of it runs; pre(tb) runs before
 // the rows of block tb.
 template <int F, typename At, typename Body, typename Pre, typename Init>
@@ -147,6 +122,14 @@ __device__ __forceinline__ void stream_blocks(At at, int t0, int t1, Body&& body
         pre(tb);
         const int lo = t0 - tb > 0 ? t0 - tb : 0, hi = t1 - tb < F ? t1 - tb : F;
         const uint32_t in = ((1u << hi) - 1u) & ~((1u << lo) - 1u);  // rows of the block in range
+        // In a partial block (wave-uniform branch, once per block) the rows
+        // outside the range become missing, so that a row's observed() alone
+        // decides whether it takes part: whole blocks test nothing per row.
+        if (lo > 0 || hi < F) {
+#pragma unroll
+            for (int u = 0; u < F; ++u)
+                if (((in >> u) & 1u) == 0) buf[u] = missing(buf[u]);
+        }
 #pragma unroll
         for (int u = 0; u < F; ++u) body(u, tb + u, buf[u], ((in >> u) & 1u) != 0);
     };
@@ -298,8 +281,8 @@ masked_periodic_kernel(MaskedArgs a)
     };
     stream_blocks<F>(
         [&](int t) { return Cur::at(a, t, lane); }, 0, n,
-        [&](int u, int t, V val, bool in) {
-            const bool ok = in && observed(val);
+        [&](int u, int t, V val, bool) {
+            const bool ok = observed(val);  // rows outside the range arrive missing
             const float v = value(val);
             if (EXPLICIT) bad = bad || (ok && !isfinite(v));
             // Lanes whose row is missing sit this one out (execution mask, no selects).
@@ -549,7 +532,7 @@ masked_periodic_kernel(MaskedArgs a)
     stream_blocks<F>(
         [&](int t) { return Cur::at(a, t, lane); }, n, N,
         [&](int u, int t, V val, bool in) {
-            const bool ok = in && observed(val);
+            const bool ok = observed(val);  // rows outside the range arrive missing
             const float v = value(val);
             if (EXPLICIT) bad = bad || (ok && !isfinite(v));
             if (ok) {  // lanes whose row is missing sit this one out

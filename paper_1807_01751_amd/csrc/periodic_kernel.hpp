@@ -290,8 +290,8 @@ void periodic_kernel(PeriodicArgs a)
         const double num = Sp - Pw[u];
         const int m = t - n;
         brk = fabs(num) > thr ? min(brk, m) : brk;
-        hi = fmax(hi, num);
-        lo = fmin(lo, num);
+        hi = max_num(hi, num);
+        lo = min_num(lo, num);
         if (EXPORT && a.mosum && active)
             put_out(a.mosum, (int64_t)m * a.P + lane, num / scale, a.out_f64);
     };
@@ -578,8 +578,8 @@ __global__ __launch_bounds__(kPlainBlock * NS) void periodic_split_kernel(Period
             const double num = Sp - Pw[u];
             const int m = t - n;
             brk = fabs(num) > thr ? min(brk, m) : brk;
-            hi = fmax(hi, num);
-            lo = fmin(lo, num);
+            hi = max_num(hi, num);
+            lo = min_num(lo, num);
             if (EXPORT && a.mosum && active)
                 put_out(a.mosum, (int64_t)m * a.P + lane, num / scale, a.out_f64);
         };

@@ -166,8 +166,8 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
         // Branch-free, so a whole chunk of rows stays one basic block and the
         // independent dot products of different rows can be interleaved.
         brk = fabs(num) > thr ? min(brk, m) : brk;
-        hi = fmax(hi, num);
-        lo = fmin(lo, num);
+        hi = max_num(hi, num);
+        lo = min_num(lo, num);
         if (EXPORT && a.mosum && active)
             put_out(a.mosum, (int64_t)m * a.P + lane, num / scale, a.out_f64);
     };
