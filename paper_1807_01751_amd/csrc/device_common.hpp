@@ -203,56 +203,79 @@ using FlaggedCursor = FlaggedCursorT<float>;
 // Streams rows [t0, t1) of one pixel column; `cur` must point at row t0.
 // Rows are fetched in chunks of U, one chunk ahead of the arithmetic, with two
 // register buffers used in turn.  Before the rows [t, t + count) of a chunk
-// are handed over, pre(t, count) runs (count is U, or 1 for the last rows);
-// then body(u, t + u, value) runs for each row, u being the row's position in
-// the chunk (a compile-time constant after unrolling).
+// are handed over, pre(t, count) runs; then body(u, t + u, value) runs for each
+// row, u being the row's position in the chunk (a compile-time constant after
+// unrolling).  The loop over full chunks is straight-line code, so the
+// compiler's wait counts keep the next chunk's loads in flight while a chunk
+// is processed.  The last chunk may be short: it is fetched ahead like the
+// others, its positions past t1 re-reading its last row (never handed over),
+// so no row at the end of a stream waits for its load alone.
 template <int U, typename Cursor, typename Body, typename Pre>
 __device__ __forceinline__ void stream_rows(Cursor cur, int t0, int t1, Body&& body, Pre&& pre)
 {
     using V = typename Cursor::value_type;
-    int t = t0;
-    if (t1 - t >= U) {
-        V a[U], b[U];
+    auto load_full = [&](V* buf) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) a[u] = cur.load(u);
+        for (int u = 0; u < U; ++u) buf[u] = cur.load(u);
         cur.advance(U);
-        for (; t + 3 * U <= t1; t += 2 * U) {
+    };
+    auto load_part = [&](V* buf, int count) {  // 1 <= count < U
+        // The index of the positions past the end is opaque to the compiler,
+        // so that no position is proved equal to another and turned into a
+        // register copy (which would wait for the load).  Inline-asm results
+        // count as divergent, hence the readfirstlane.
+        int last = __builtin_amdgcn_readfirstlane(count - 1);
+        asm volatile("" : "+s"(last));
+        last = __builtin_amdgcn_readfirstlane(last);
 #pragma unroll
-            for (int u = 0; u < U; ++u) b[u] = cur.load(u);
-            cur.advance(U);
-            pre(t, U);
+        for (int u = 0; u < U; ++u) buf[u] = cur.load(u < count ? u : last);
+        cur.advance(count);
+    };
+    auto run_full = [&](const V* buf, int t) {
+        pre(t, U);
 #pragma unroll
-            for (int u = 0; u < U; ++u) body(u, t + u, a[u]);
+        for (int u = 0; u < U; ++u) body(u, t + u, buf[u]);
+    };
+    auto run_part = [&](const V* buf, int t, int count) {  // 1 <= count < U
+        pre(t, count);
 #pragma unroll
-            for (int u = 0; u < U; ++u) a[u] = cur.load(u);
-            cur.advance(U);
-            pre(t + U, U);
-#pragma unroll
-            for (int u = 0; u < U; ++u) body(u, t + U + u, b[u]);
+        for (int u = 0; u < U; ++u)
+            if (u < count) body(u, t + u, buf[u]);
+    };
+    V a[U], b[U];
+    if (t1 - t0 < U) {
+        if (t1 > t0) {
+            load_part(a, t1 - t0);
+            run_part(a, t0, t1 - t0);
         }
-        if (t + 2 * U <= t1) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) b[u] = cur.load(u);
-            cur.advance(U);
-            pre(t, U);
-#pragma unroll
-            for (int u = 0; u < U; ++u) body(u, t + u, a[u]);
-            pre(t + U, U);
-#pragma unroll
-            for (int u = 0; u < U; ++u) body(u, t + U + u, b[u]);
-            t += 2 * U;
-        } else {
-            pre(t, U);
-#pragma unroll
-            for (int u = 0; u < U; ++u) body(u, t + u, a[u]);
-            t += U;
-        }
+        return;
     }
-    for (; t < t1; ++t) {
-        const V v = cur.load(0);
-        cur.advance(1);
-        pre(t, 1);
-        body(0, t, v);
+    int t = t0;
+    load_full(a);
+    for (; t + 3 * U <= t1; t += 2 * U) {
+        load_full(b);
+        run_full(a, t);
+        load_full(a);
+        run_full(b, t + U);
+    }
+    // a holds the full chunk at t; U <= t1 - t < 3U rows remain.
+    const int R = t1 - t;
+    if (R > 2 * U) {
+        load_full(b);
+        run_full(a, t);
+        load_part(a, R - 2 * U);
+        run_full(b, t + U);
+        run_part(a, t + 2 * U, R - 2 * U);
+    } else if (R == 2 * U) {
+        load_full(b);
+        run_full(a, t);
+        run_full(b, t + U);
+    } else if (R > U) {
+        load_part(b, R - U);
+        run_full(a, t);
+        run_part(b, t + U, R - U);
+    } else {
+        run_full(a, t);
     }
 }
 
@@ -261,6 +284,26 @@ __device__ __forceinline__ void stream_rows(Cursor cur, int t0, int t1, Body&& b
 {
     stream_rows<U>(cur, t0, t1, [&](int, int t, typename Cursor::value_type v) { body(t, v); },
                    [](int, int) {});
+}
+
+// A lean form for rarely taken passes: chunks of U rows, each chunk's loads
+// issued together (the last chunk's positions past t1 re-read row t1 - 1) and
+// then its rows processed, with no fetch ahead of the arithmetic; one copy of
+// the body, so that such a pass adds little code.
+template <int U, typename Cursor, typename Body>
+__device__ __forceinline__ void stream_rows_lean(Cursor cur, int t0, int t1, Body&& body)
+{
+    using V = typename Cursor::value_type;
+    for (int t = t0; t < t1; t += U) {
+        const int count = t1 - t < U ? t1 - t : U;
+        V buf[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) buf[u] = cur.load(u < count ? u : count - 1);
+        cur.advance(count);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (u < count) body(t + u, buf[u]);
+    }
 }
 
 // Streams rows [t0, t1) in blocks aligned to multiples of F in absolute time:

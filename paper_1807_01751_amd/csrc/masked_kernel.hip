@@ -34,7 +34,12 @@ namespace {
 using namespace dev;
 
 constexpr int kMaskedBlock = 64;  // one wave per workgroup
-constexpr int kMU = 16;           // rows per prefetch chunk
+#ifndef BFM_MASKED_ROWS
+#define BFM_MASKED_ROWS 8
+#endif
+// Rows per prefetch chunk: each row's design and Gram-table entries are held
+// in scalar registers while it is processed, so longer chunks spill them.
+constexpr int kMU = BFM_MASKED_ROWS;
 
 template <int K, bool EXPORT, bool EXPLICIT>
 __global__ __launch_bounds__(kMaskedBlock) void masked_kernel(MaskedArgs a)
@@ -143,11 +148,11 @@ __global__ __launch_bounds__(kMaskedBlock) void masked_kernel(MaskedArgs a)
             }
         };
         if (EXPLICIT)
-            stream_rows<kMU>(FlaggedCursor{Y, a.valid, ld, a.ldv, lane}, 0, n,
-                             [&](int t, FlaggedObs o) { row2(t, o.y, o.ok != 0); });
+            stream_rows_lean<kMU>(FlaggedCursor{Y, a.valid, ld, a.ldv, lane}, 0, n,
+                                  [&](int t, FlaggedObs o) { row2(t, o.y, o.ok != 0); });
         else
-            stream_rows<kMU>(ObsCursor{Y, ld, lane * 4u}, 0, n,
-                             [&](int t, float v) { row2(t, v, isfinite(v)); });
+            stream_rows_lean<kMU>(ObsCursor{Y, ld, lane * 4u}, 0, n,
+                                  [&](int t, float v) { row2(t, v, isfinite(v)); });
         rss = refine ? rr - Gk::refine(L, dq, beta, refine) : rss;
     }
     const double sig = sqrt(fmax(rss, 0.0) / (double)(nv - NP));

@@ -411,11 +411,11 @@ masked_periodic_kernel(MaskedArgs a)
         };
         const T* const Yt = static_cast<const T*>(a.Y);
         if (EXPLICIT)
-            stream_rows<8>(FlaggedCursorT<T>{Yt, a.valid, a.ld, a.ldv, lane}, 0, n,
-                           [&](int t, FlaggedObs o) { row2(t, o.y, o.ok != 0); });
+            stream_rows_lean<8>(FlaggedCursorT<T>{Yt, a.valid, a.ld, a.ldv, lane}, 0, n,
+                                [&](int t, FlaggedObs o) { row2(t, o.y, o.ok != 0); });
         else
-            stream_rows<8>(ObsCursorT<T>{Yt, a.ld, lane * (uint32_t)sizeof(T)}, 0, n,
-                           [&](int t, float v) { row2(t, v, isfinite(v)); });
+            stream_rows_lean<8>(ObsCursorT<T>{Yt, a.ld, lane * (uint32_t)sizeof(T)}, 0, n,
+                                [&](int t, float v) { row2(t, v, isfinite(v)); });
         rss = refine ? rr - Gk::refine(L, dq, beta, refine) : rss;
     }
     const double sig = sqrt(fmax(rss, 0.0) / (double)(nv - NP));

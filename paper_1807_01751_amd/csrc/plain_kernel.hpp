@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
 #pragma unroll
         for (int j = 0; j < NP; ++j) db[j] = 0.0;
         Filler fill2{c0};
-        stream_rows<kU>(ObsCursor{Y, ld, lane_bytes}, 0, n, [&](int t, float v) {
+        stream_rows_lean<kU>(ObsCursor{Y, ld, lane_bytes}, 0, n, [&](int t, float v) {
             if (FILL) v = fill2(v);
             const ctab qt = q + t * NP;
             double r = (double)v - c;
