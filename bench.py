@@ -7,10 +7,10 @@ lambda = 2.5, f = 23, seeded synthetic season-trend series with 20% planted
 steps (see paper_1807_01751_amd/synth.py).  Y is device-resident before the
 timed region; one step is one bfm_fit_monitor call over the whole tile
 (fit, sigma, MOSUM, boundary test, break index and magnitude), FP64 arithmetic.
-Before the W warmup steps the step runs untimed for at least a quarter of a
-second: the first tens of milliseconds of work after the GPU was idle run at
-lower clocks (measured: the same launch 2x slower in the first batch, steady
-after about 50 ms).
+Before the W warmup steps of every leg the step runs untimed for at least a
+quarter of a second: the first tens of milliseconds of work after the GPU was
+idle run at lower clocks (measured: the same launch 2x slower in the first
+batch, steady after about 50 ms).
 
 After the headline leg, the same tile with 25% of its observations missing
 (NaN: half independent, half cloud runs of 3-15 rows) is timed through the
@@ -411,14 +411,33 @@ def bench_line_note(path, leg, avg_ns):
             f"{avg_ns / 1e6:.4f} ms.")
 
 
+PREWARM_S = 0.25  # --prewarm-s
+
+
+def prewarm(step, seconds):
+    """Runs ``step`` untimed, synchronising after each call, for ``seconds``;
+    returns the number of calls."""
+    import torch
+    t0, k = time.perf_counter(), 0
+    while time.perf_counter() - t0 < seconds:
+        step()
+        torch.cuda.synchronize()
+        k += 1
+    return k
+
+
 def timed(step, steps, warmup, stream):
-    """Warm up, then time exactly ``steps`` calls back to back: wall clock over
+    """Run the step untimed for PREWARM_S seconds (the clocks ramp up over the
+    first tens of milliseconds of work: without it a leg of ten 1.3 ms steps
+    read 1.37 instead of 1.15 ms per step), warm up, then time exactly
+    ``steps`` calls back to back: wall clock over
     all of them, and two HIP events on the stream the kernel runs on around the
     whole region (their span / steps is the mean launch duration).  Per-launch
     latencies (p50, p99) come from a separate pass of as many calls, each
     bracketed by its own events (which add a short gap between launches, so they
     are kept out of the timed region)."""
     import torch
+    prewarm(step, PREWARM_S)
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
@@ -708,14 +727,9 @@ def main():
                         outputs=("brk", "mag"), out_dtype=torch.float32, out=out)
 
     stream = torch.cuda.current_stream(dev)
-    t_warm = time.perf_counter()
-    warm_steps = 0
-    while time.perf_counter() - t_warm < args.prewarm_s:
-        step()
-        torch.cuda.synchronize()
-        warm_steps += 1
-    log(f"bench: pre-warm {warm_steps} steps in {time.perf_counter() - t_warm:.2f} s")
-    log(f"bench: plain leg, warmup {args.warmup}, timing {args.steps} steps")
+    global PREWARM_S
+    PREWARM_S = args.prewarm_s
+    log(f"bench: plain leg, pre-warm {PREWARM_S} s, warmup {args.warmup}, timing {args.steps} steps")
     tp = timed(step, args.steps, args.warmup, stream)
     log(f"bench: {tp['ms_per_step']:.4f} ms/step wall, kernel mean {tp['mean']:.4f} ms")
     ref = {k: v.clone() for k, v in out.items()}
