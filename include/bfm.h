@@ -226,21 +226,32 @@ int bfm_fit_monitor_typed(bfm_ctx *ctx, const bfm_params *prm, const void *Y, in
                           const bfm_outputs *out, void *stream);
 
 /*
- * Tile-shape tuning of the plain path.  For f in {12, 23, 24}, a float32
- * series and no per-row exports (resid, mosum), the plain path may give each
- * group of 64 pixels 1, 2, 4 or 8 waves that stream consecutive
- * shares of its rows (the history sums add up over the shares; each share of
- * the monitoring period rebuilds its MOSUM window from the H rows before it):
- * a long series over few pixels then finishes sooner.  By default each group
- * of 64 pixels has one wave (the fastest for the usual tile shapes on MI355X,
- * measured); bfm_autotune times every
- * split that fits (on Y, with scratch outputs, synchronising `stream`) and
- * keeps the fastest for this tile shape (the parameters, y_dtype and the
- * power-of-two bucket of P/64) in the context; bfm_tune_set pins a split for a
- * shape.  Results differ between splits only by the rounding of the history
- * sums.  times_us (nullable, 4 entries) receives the median time of splits 1,
- * 2, 4, 8 (0 where not run).  Both return BFM_E_UNSUPPORTED where the
- * parameters do not take the period-blocked plain kernel.
+ * Tile-shape tuning.  Plain path: for f in {12, 23, 24}, a float32 series and
+ * no per-row exports (resid, mosum), each group of 64 pixels may get 1, 2, 4 or
+ * 8 waves that stream consecutive shares of its rows (the history sums add up
+ * over the shares; each share of the monitoring period rebuilds its MOSUM
+ * window from the H rows before it): a long series over few pixels then
+ * finishes sooner.  By default each group of 64 pixels has one wave (the
+ * fastest for the usual tile shapes on MI355X, measured).
+ * Missing-value path (BFM_MASK_NAN, BFM_MASK_EXPLICIT) with f in {12, 23, 24}
+ * (the period-blocked kernel): the split covers the history; wave w of a group
+ * streams the w-th share of the history's blocks of f rows, the waves hand
+ * their partial sums on in wave order, and the last wave fits and monitors
+ * (its window's observations taken from the earlier shares where its own share
+ * holds fewer than H).  A split needs a block of f history rows per wave and
+ * LDS for every wave's window ring plus the staging of the sums; by default
+ * the split is 1.
+ * bfm_autotune times every split that fits (on Y, with scratch outputs,
+ * synchronising `stream`; on the missing-value path the BFM_MASK_NAN mode only,
+ * as no validity mask is passed) and keeps the fastest for this tile shape (the
+ * parameters, the mask mode, y_dtype and the power-of-two bucket of P/64) in
+ * the context; bfm_tune_set pins a split for a shape (both mask modes).
+ * Results differ between splits only by the rounding of the history sums.
+ * times_us (nullable, 4 entries) receives the median time of splits 1, 2, 4, 8
+ * (0 where not run).  Both return BFM_E_UNSUPPORTED where the parameters take
+ * neither period-blocked kernel (and bfm_autotune for BFM_MASK_EXPLICIT), and
+ * bfm_tune_set also where the split does not fit (LDS, or more waves than
+ * history blocks); BFM_E_INVAL for a split other than 1, 2, 4 or 8.
  */
 int bfm_autotune(bfm_ctx *ctx, const bfm_params *prm, const void *Y, int32_t y_dtype, int64_t P,
                  int64_t ld, void *stream, int32_t *split, double *times_us);

@@ -350,12 +350,13 @@ def critical_value_noalloc(alpha: float, *, n: int, N: int, h: float = 0.25, h_w
 
 
 def autotune(Y: torch.Tensor, *, n: int, order: int = 3, freq: float = 23.0, h: float = 0.25,
-             h_window: int = 0, lam: float = 2.5, stream=None):
-    """bfm_autotune: time the row splits of the plain path on Y and keep the
-    fastest for this tile shape.  Returns (split, {split: median us})."""
+             h_window: int = 0, lam: float = 2.5, mask_mode: int = MASK_NONE, stream=None):
+    """bfm_autotune: time the row splits on Y (the plain path, or with
+    ``mask_mode=MASK_NAN`` the history split of the missing-value path) and keep
+    the fastest for this tile shape.  Returns (split, {split: median us})."""
     Y, N, P, ld = _series_layout(Y)
     dev = Y.device.index if Y.device.index is not None else torch.cuda.current_device()
-    prm = make_params(N, n, order, freq, h, h_window, lam, MASK_NONE)
+    prm = make_params(N, n, order, freq, h, h_window, lam, mask_mode)
     s = stream if stream is not None else torch.cuda.current_stream(Y.device)
     split = ctypes.c_int32()
     times = (ctypes.c_double * 4)()
@@ -365,11 +366,12 @@ def autotune(Y: torch.Tensor, *, n: int, order: int = 3, freq: float = 23.0, h: 
 
 
 def tune_set(Y: torch.Tensor, split: int, *, n: int, order: int = 3, freq: float = 23.0,
-             h: float = 0.25, h_window: int = 0, lam: float = 2.5):
-    """bfm_tune_set: pin the row split of the plain path for Y's tile shape."""
+             h: float = 0.25, h_window: int = 0, lam: float = 2.5, mask_mode: int = MASK_NONE):
+    """bfm_tune_set: pin the row split for Y's tile shape (the plain path, or
+    the missing-value path's history split with MASK_NAN / MASK_EXPLICIT)."""
     Y, N, P, ld = _series_layout(Y)
     dev = Y.device.index if Y.device.index is not None else torch.cuda.current_device()
-    prm = make_params(N, n, order, freq, h, h_window, lam, MASK_NONE)
+    prm = make_params(N, n, order, freq, h, h_window, lam, mask_mode)
     _raise(load().bfm_tune_set(context(dev), ctypes.byref(prm), _Y_DTYPES[Y.dtype], P, int(split)))
 
 

@@ -51,9 +51,10 @@ struct bfm_ctx {
     // (N, n, k, h_window, f, h_frac, lambda, hash of the observation times or 0)
     using Key = std::tuple<int, int, int, int, double, double, double, uint64_t>;
     std::map<Key, Entry> plain;
-    // Autotuned time split of the period-blocked plain kernel, per tile shape:
-    // (order, F, H, N, n, y_dtype, ceil(log2(waves))) -> waves per 64 pixels.
-    using TuneKey = std::tuple<int, int, int, int, int, int, int>;
+    // Autotuned time split of the period-blocked plain and missing-value
+    // kernels, per tile shape: (order, F, H (plain) or ring capacity (missing
+    // values), N, n, y_dtype, ceil(log2(waves)), mask mode) -> waves per 64 pixels.
+    using TuneKey = std::tuple<int, int, int, int, int, int, int, int>;
     std::map<TuneKey, int> tune;
     struct MEntry {
         bfm::MaskedOps ops;
@@ -142,7 +143,7 @@ int log2_ceil(int64_t v)
 
 bfm_ctx::TuneKey tune_key(const bfm_params& p, int y_dtype, int64_t P, int H, int F)
 {
-    return bfm_ctx::TuneKey{p.order, F, H, p.n_obs, p.n_hist, y_dtype, log2_ceil((P + 63) / 64)};
+    return bfm_ctx::TuneKey{p.order, F, H, p.n_obs, p.n_hist, y_dtype, log2_ceil((P + 63) / 64), p.mask_mode};
 }
 
 // Waves per 64 pixels that share a pixel's rows in the period-blocked plain
@@ -391,7 +392,18 @@ int fit_masked(bfm_ctx* ctx, const bfm_params& p, const void* Y, int y_dtype, in
     if (y_dtype != BFM_Y_F32 && !blocked)
         return fail(BFM_E_UNSUPPORTED, "a 16-bit series needs f in {12, 23, 24}, n_hist <= %d and "
                     "ld * 4 * f < 2^31 on the missing-value path", bfm::kMaskedPeriodicMaxHist);
-    const size_t lds = blocked ? bfm::masked_periodic_lds_bytes(ops.cap) : bfm::masked_lds_bytes(ops.cap);
+    // History split of the period-blocked kernel: the tuned (or pinned) choice
+    // for this tile shape, else one wave per 64 pixels.
+    int split = 1;
+    if (blocked) {
+        auto tt = ctx->tune.find(tune_key(p, y_dtype, P, ops.cap, ops.F));
+        if (tt != ctx->tune.end()) split = tt->second;
+        if (split > (p.n_hist + ops.F - 1) / ops.F ||
+            bfm::masked_periodic_lds_bytes(ops.cap, ops.F, split) > ctx->max_lds)
+            split = 1;
+    }
+    const size_t lds = blocked ? bfm::masked_periodic_lds_bytes(ops.cap, ops.F, split)
+                               : bfm::masked_lds_bytes(ops.cap);
     if (lds > ctx->max_lds)
         return fail(BFM_E_UNSUPPORTED, "window H=%d needs %zu B of LDS per workgroup (max %zu)",
                     ops.Hmax, lds, ctx->max_lds);
@@ -407,6 +419,7 @@ int fit_masked(bfm_ctx* ctx, const bfm_params& p, const void* Y, int y_dtype, in
     a.ph = a.g + ops.g.size();
     a.F = ops.F;
     a.m32 = p.precision == BFM_PREC_FP32;
+    a.split = split;
     a.N = p.n_obs;
     a.n = p.n_hist;
     a.h_window = p.h_window;
@@ -734,9 +747,22 @@ int split_shape(bfm_ctx* ctx, const bfm_params* prm, int32_t y_dtype, int64_t P,
     if (rc) return rc;
     if (y_dtype != BFM_Y_F32 && y_dtype != BFM_Y_BF16 && y_dtype != BFM_Y_F16)
         return fail(BFM_E_INVAL, "unknown y_dtype %d", y_dtype);
+    if (prm->mask_mode == BFM_MASK_NAN || prm->mask_mode == BFM_MASK_EXPLICIT) {
+        // The history split of the period-blocked missing-value kernel.
+        bfm::MaskedOps ops;
+        bfm::build_masked_ops(*prm, &ops);
+        const int64_t lim = (int64_t)1 << 31;
+        if (ops.F == 0 || ld * 4 * ops.F >= lim ||
+            bfm::masked_periodic_lds_bytes(ops.cap, ops.F, 1) > ctx->max_lds)
+            return fail(BFM_E_UNSUPPORTED, "these parameters do not take the period-blocked "
+                        "missing-value kernel");
+        *H = ops.cap;
+        *F = ops.F;
+        return BFM_SUCCESS;
+    }
     if (prm->mask_mode != BFM_MASK_NONE || y_dtype != BFM_Y_F32)
-        return fail(BFM_E_UNSUPPORTED, "tile tuning applies to the plain path (no missing-value "
-                    "handling) on float32 series");
+        return fail(BFM_E_UNSUPPORTED, "tile tuning applies to the plain path on float32 series and "
+                    "to the missing-value path with f in {12, 23, 24}");
     std::lock_guard<std::mutex> lock(ctx->mu);
     DeviceGuard g(ctx->device);
     bfm_ctx::Entry* ent = nullptr;
@@ -750,6 +776,16 @@ int split_shape(bfm_ctx* ctx, const bfm_params* prm, int32_t y_dtype, int64_t P,
     *H = ent->ops.H;
     *F = ent->per.F;
     return BFM_SUCCESS;
+}
+
+// Whether `split` waves per 64 pixels fit the kernel that split_shape found
+// (H: the plain window, or the missing-value ring capacity).
+bool split_fits(bfm_ctx* ctx, const bfm_params* prm, int split, int H, int F)
+{
+    if (prm->mask_mode == BFM_MASK_NAN || prm->mask_mode == BFM_MASK_EXPLICIT)
+        return split <= (prm->n_hist + F - 1) / F &&
+               bfm::masked_periodic_lds_bytes(H, F, split) <= ctx->max_lds;
+    return bfm::periodic_split_lds(prm->order, F, split, H) <= ctx->max_lds;
 }
 
 }  // namespace
@@ -860,8 +896,9 @@ int bfm_tune_set(bfm_ctx* ctx, const bfm_params* prm, int32_t y_dtype, int64_t P
     if (rc) return rc;
     if (split != 1 && split != 2 && split != 4 && split != 8)
         return fail(BFM_E_INVAL, "split must be 1, 2, 4 or 8 (got %d)", split);
-    if (bfm::periodic_split_lds(prm->order, F, split, H) > ctx->max_lds)
-        return fail(BFM_E_UNSUPPORTED, "split %d needs more LDS than a workgroup has", split);
+    if (!split_fits(ctx, prm, split, H, F))
+        return fail(BFM_E_UNSUPPORTED, "split %d needs more LDS than a workgroup has, or more waves than "
+                    "the history has blocks", split);
     std::lock_guard<std::mutex> lock(ctx->mu);
     ctx->tune[tune_key(*prm, y_dtype, P, H, F)] = split;
     return BFM_SUCCESS;
@@ -874,6 +911,9 @@ int bfm_autotune(bfm_ctx* ctx, const bfm_params* prm, const void* Y, int32_t y_d
     int rc = split_shape(ctx, prm, y_dtype, P, ld, &H, &F);
     if (rc) return rc;
     if (P < 1 || !Y) return fail(BFM_E_INVAL, "autotune needs P >= 1 and Y");
+    if (prm->mask_mode == BFM_MASK_EXPLICIT)
+        return fail(BFM_E_UNSUPPORTED, "autotune times the NaN mask mode (no validity mask is passed); "
+                    "pin a split for BFM_MASK_EXPLICIT with bfm_tune_set");
     DeviceGuard g(ctx->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
     bfm_outputs out{};
@@ -888,7 +928,7 @@ int bfm_autotune(bfm_ctx* ctx, const bfm_params* prm, const void* Y, int32_t y_d
     int best = 0;
     const auto key = tune_key(*prm, y_dtype, P, H, F);
     for (int i = 0; i < 4 && e == hipSuccess && rc == BFM_SUCCESS; ++i) {
-        if (bfm::periodic_split_lds(prm->order, F, cand[i], H) > ctx->max_lds) continue;
+        if (!split_fits(ctx, prm, cand[i], H, F)) continue;
         {
             std::lock_guard<std::mutex> lock(ctx->mu);
             ctx->tune[key] = cand[i];

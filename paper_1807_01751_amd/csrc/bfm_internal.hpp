@@ -83,6 +83,9 @@ struct MaskedOps {
 // integer counters are exact up to there, and a history row index fits the
 // 16-bit field of its window ring).
 constexpr int kMaskedPeriodicMaxHist = 8192;
+// Waves per 64 pixels that may share the history rows of the period-blocked
+// missing-value kernel (its history split: 1, 2, 4 or 8).
+constexpr int kMaskedMaxSplit = 8;
 bool build_masked_ops(const bfm_params& prm, MaskedOps* ops);
 
 // Centre and scale of the trend column of the design (tau = (t - tc) / ts):
@@ -168,6 +171,7 @@ struct MaskedArgs {
     const double* ph;      // F x 4k (period-blocked kernel)
     int F;                 // 0: general kernel
     int m32;               // BFM_PREC_FP32: the period-blocked kernel's MOSUM in FP32
+    int split;             // period-blocked kernel: waves per 64 pixels sharing the history (1, 2, 4, 8)
     int N, n, h_window, cap;
     double h_frac, lambda;
     double tc, ts;         // time centre and scale of the trend column: tau = (t - tc) / ts
@@ -187,7 +191,7 @@ hipError_t launch_masked_periodic_bf16(const MaskedArgs& a, int order, int mask_
 hipError_t launch_masked_periodic_f16(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
 hipError_t launch_masked_periodic_m32(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
 hipError_t launch_masked_periodic_m32_f16(const MaskedArgs& a, int order, int mask_mode, hipStream_t stream);
-size_t masked_periodic_lds_bytes(int cap);
+size_t masked_periodic_lds_bytes(int cap, int F, int split);
 size_t masked_lds_bytes(int cap);
 
 // Null-path MOSUM sup statistics for the simulated critical value (one lane per

@@ -51,7 +51,7 @@ namespace {
 
 using namespace dev;
 
-constexpr int kBlock = 64;           // one wave per workgroup
+constexpr int kBlock = 64;           // pixels per workgroup (one wave, or `split` waves)
 constexpr uint32_t kCountBits = 12;  // acc_r = W_r + (Q_r << 12)
 constexpr uint32_t kCountMask = (1u << kCountBits) - 1;
 
@@ -204,13 +204,21 @@ struct CursorOf<true, T> {
 // LDS is what limits residency (one ring slot per window position and lane),
 // so the kernel may use up to 256 VGPRs without losing waves.
 //
+// History split (a.split = S > 1 waves per 64 pixels, for tiles with few
+// pixels): wave w streams its share of the history blocks and keeps its own
+// sums and ring.  The history sums add up over the shares (the per-pixel sum
+// of squared block indices by parts with a cross term for the observations of
+// the earlier shares), so the waves hand their partial sums on in wave order
+// through LDS; the last wave then also takes the observations its window needs
+// from the rings of the earlier shares, fits, and monitors alone.
+//
 // M32 (BFM_PREC_FP32): the MOSUM in FP32.  The fit, sigma and each residual are
 // computed in FP64 as above; the residual is then rounded to float, kept in the
 // ring's 32-bit word (no 16-bit word: one LDS write and one read per row), and
 // the window sum, its extremes and the boundary test run in FP32 (the paper's
 // own MOSUM kernel computes in float).
 template <int K, int F, bool EXPORT, bool EXPLICIT, typename T, bool M32>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void
+__global__ __launch_bounds__(kBlock * kMaskedMaxSplit) __attribute__((amdgpu_waves_per_eu(2))) void
 masked_periodic_kernel(MaskedArgs a)
 {
     using Acc = typename std::conditional<M32, float, double>::type;  // MOSUM arithmetic
@@ -224,15 +232,23 @@ masked_periodic_kernel(MaskedArgs a)
     // slots hold a residual kept to 36 mantissa bits (the low 16 bits cleared
     // before it enters the MOSUM, so it leaves the sum exactly as it entered).
     extern __shared__ uint32_t ring_hi[];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x & (kBlock - 1);
+    const int NS = (int)(blockDim.x / kBlock);                              // waves per 64 pixels
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kBlock));  // this wave's share
     const int64_t pix = (int64_t)blockIdx.x * kBlock + tid;
     const bool active = pix < a.P;
     const uint32_t lane = (uint32_t)(active ? pix : a.P - 1);
     const int n = a.n, N = a.N;
     const int cap = ring_slots(a.cap);  // the longest window: rows are written only when observed
     const ctab ph = as_const(a.ph);
-    uint32_t* const rhi = ring_hi + tid;
-    uint16_t* const rmid = reinterpret_cast<uint16_t*>(ring_hi + cap * kBlock) + tid;
+    // Rings of the S waves: high words, then the 16-bit middle words.
+    uint32_t* const rhi = ring_hi + (w * cap) * kBlock + tid;
+    uint16_t* const rmid0 = reinterpret_cast<uint16_t*>(ring_hi + NS * cap * kBlock) + tid;
+    uint16_t* const rmid = rmid0 + (w * cap) * kBlock;
+    // The history blocks of this wave's share (the host keeps S <= blocks).
+    const int nblk = (n + F - 1) / F;
+    const int b0 = nblk * w / NS, b1 = nblk * (w + 1) / NS;
+    const int h0 = b0 * F, h1 = min(b1 * F, n);
     const double c0 = 0.5 * (double)(n - 1);  // tau_t = (t - c0) / n for 0-based t
 
     // ---- history rows: per-phase counts and sums ----
@@ -268,7 +284,17 @@ masked_periodic_kernel(MaskedArgs a)
         return have || any;
     };
     auto init = [&](const V* buf) {
-        bool have = first_observed(buf, 0, false);
+        bool have;
+        if (h0 == 0) {
+            have = first_observed(buf, 0, false);
+        } else {  // a later share: every wave finds the same first observation
+            const typename Cur::type cc = Cur::at(a, 0, lane);
+            const int lim = n - 1;
+            V first[F];
+#pragma unroll
+            for (int u = 0; u < F; ++u) first[u] = cc.load(u < lim ? u : lim);
+            have = first_observed(first, 0, false);
+        }
         for (int t0 = F; t0 < n && !__all(have); t0 += F) {
             const typename Cur::type cc = Cur::at(a, t0, lane);
             const int lim = n - 1 - t0;
@@ -280,7 +306,7 @@ masked_periodic_kernel(MaskedArgs a)
         c = (double)cf;
     };
     stream_blocks<F>(
-        [&](int t) { return Cur::at(a, t, lane); }, 0, n,
+        [&](int t) { return Cur::at(a, t, lane); }, h0, h1,
         [&](int u, int t, V val, bool) {
             const bool ok = observed(val);  // rows outside the range arrive missing
             const float v = value(val);
@@ -308,6 +334,55 @@ masked_periodic_kernel(MaskedArgs a)
             bd = (double)b;
         },
         init);
+
+    // ---- history split: partial sums handed on in wave order ----
+    const uint32_t cnt_own = cnt;  // observations in this wave's share (its ring)
+    if (NS > 1) {
+        // Staging after the rings: per lane, A[F], yy, Bd (FP64), then acc[F],
+        // cnt, zs, ymax, bad, then every wave's (count, next slot).
+        double* const sd = reinterpret_cast<double*>(ring_hi + NS * cap * kBlock * 3 / 2) + tid;
+        uint32_t* const su = reinterpret_cast<uint32_t*>(sd - tid + (F + 2) * kBlock) + tid;
+        uint32_t* const meta = su + (F + 4) * kBlock;
+        meta[(2 * w) * kBlock] = cnt_own;
+        meta[(2 * w + 1) * kBlock] = (uint32_t)wp;
+        // Sum of (2b - 1) over this share's blocks b >= 1: the weight of the
+        // earlier shares' count in the sum of squared block indices by parts.
+        const uint32_t bw0 = (uint32_t)(b0 > 0 ? b0 - 1 : 0), bw1 = (uint32_t)(b1 - 1);
+        const uint32_t zs_weight = bw1 * bw1 - bw0 * bw0;
+        auto take = [&]() {  // add the sums of the earlier shares
+#pragma unroll
+            for (int r = 0; r < F; ++r) {
+                A[r] = sd[r * kBlock] + A[r];
+                acc[r] += su[r * kBlock];
+            }
+            yy = sd[F * kBlock] + yy;
+            Bd = sd[(F + 1) * kBlock] + Bd;
+            const uint32_t cprev = su[F * kBlock];
+            zs += su[(F + 1) * kBlock] + cprev * zs_weight;
+            cnt += cprev;
+            ymaxb = max(ymaxb, su[(F + 2) * kBlock]);
+            bad = bad || su[(F + 3) * kBlock] != 0u;
+        };
+        for (int k = 0; k < NS - 1; ++k) {
+            if (w == k) {
+                if (k > 0) take();
+#pragma unroll
+                for (int r = 0; r < F; ++r) {
+                    sd[r * kBlock] = A[r];
+                    su[r * kBlock] = acc[r];
+                }
+                sd[F * kBlock] = yy;
+                sd[(F + 1) * kBlock] = Bd;
+                su[F * kBlock] = cnt;
+                su[(F + 1) * kBlock] = zs;
+                su[(F + 2) * kBlock] = ymaxb;
+                su[(F + 3) * kBlock] = bad ? 1u : 0u;
+            }
+            __syncthreads();
+        }
+        if (w != NS - 1) return;  // the last wave fits and monitors
+        take();
+    }
 
     // ---- Gram matrix and right-hand side from the phase sums (Eq. 5-6) ----
     const int nv = (int)cnt;
@@ -451,6 +526,52 @@ masked_periodic_kernel(MaskedArgs a)
             if (j == 0) v = beta[0] - (tc / (double)n) * beta[1] + c;
             if (j == 1) v = beta[1] / (double)n;
             put_out(a.beta, (int64_t)j * a.P + pix, have_fit ? v : qnan, a.out_f64);
+        }
+    }
+
+    // ---- history split: the window's observations from earlier shares ----
+    // A lane whose share holds fewer than H observations copies the ones before
+    // them, oldest first, from the earlier shares' rings into the free slots
+    // before its own entries, so that its window lies in its ring in time order.
+    if (NS > 1) {
+        const uint32_t* const meta = reinterpret_cast<const uint32_t*>(
+            reinterpret_cast<const double*>(ring_hi + NS * cap * kBlock * 3 / 2) + (F + 2) * kBlock) +
+            (F + 4) * kBlock + tid;
+        auto cnt_of = [&](int v) { return (int)meta[(2 * v) * kBlock]; };
+        auto wp_of = [&](int v) { return (int)meta[(2 * v + 1) * kBlock]; };
+        const int want = monitor && (int)cnt_own < H ? H - (int)cnt_own : 0;
+        int most = want;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) most = max(most, __shfl_xor(most, o));
+        most = __builtin_amdgcn_readfirstlane(most);
+        if (most > 0) {
+            int sw = NS - 2, need = want;
+            while (sw > 0 && cnt_of(sw) < need) {
+                need -= cnt_of(sw);
+                --sw;
+            }
+            int ss = wp_of(sw) - need;
+            ss += ss < 0 ? cap : 0;
+            int rem = need;
+            int d = wp - H;
+            d += d < 0 ? cap : 0;
+            for (int i = 0; i < most; ++i) {
+                if (i < want) {
+                    const int src = (sw * cap + ss) * kBlock;
+                    rhi[d * kBlock] = ring_hi[src + tid];
+                    rmid[d * kBlock] = rmid0[src];
+                    d = d + 1 == cap ? 0 : d + 1;
+                    ss = ss + 1 == cap ? 0 : ss + 1;
+                    if (--rem == 0 && i + 1 < want) {
+                        do {
+                            ++sw;
+                        } while (cnt_of(sw) == 0);
+                        rem = cnt_of(sw);
+                        ss = wp_of(sw) - rem;
+                        ss += ss < 0 ? cap : 0;
+                    }
+                }
+            }
         }
     }
 
@@ -599,14 +720,19 @@ template <int K, int F, bool EXPLICIT, typename T, bool M32>
 hipError_t launch_kf(const MaskedArgs& a, hipStream_t stream)
 {
     const dim3 grid((unsigned)((a.P + kBlock - 1) / kBlock));
-    const size_t lds = (size_t)ring_slots(a.cap) * kBlock * 6;
+    const int split = a.split > 0 ? a.split : 1;
+    // The rings, and with a split the staging after them (host-checked sizes).
+    const size_t lds = (size_t)split * ring_slots(a.cap) * kBlock * 6 +
+                       (split > 1 ? (size_t)kBlock * (8 * (F + 2) + 4 * (F + 4) + 8 * split) : 0);
     if (a.n >= 65536) return hipErrorInvalidValue;  // history rows are kept as 16-bit indices
+    if (split > kMaskedMaxSplit || split > (a.n + F - 1) / F) return hipErrorInvalidValue;  // a block per wave
+    const dim3 block((unsigned)(kBlock * split));
     if (a.resid || a.mosum)
-        hipLaunchKernelGGL((masked_periodic_kernel<K, F, true, EXPLICIT, T, M32>), grid, dim3(kBlock), lds,
-                           stream, a);
+        hipLaunchKernelGGL((masked_periodic_kernel<K, F, true, EXPLICIT, T, M32>), grid, block, lds, stream,
+                           a);
     else
-        hipLaunchKernelGGL((masked_periodic_kernel<K, F, false, EXPLICIT, T, M32>), grid, dim3(kBlock), lds,
-                           stream, a);
+        hipLaunchKernelGGL((masked_periodic_kernel<K, F, false, EXPLICIT, T, M32>), grid, block, lds, stream,
+                           a);
     return hipGetLastError();
 }
 
