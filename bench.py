@@ -28,7 +28,9 @@ million no-change paths (lambda).
 
 Two more legs follow: the small tile of the first configuration (64 x 64
 pixels, N = 228) timed call by call, warm and with the L2 caches and the MALL
-flushed before each call ("latency_tile"), and the largest tile (4096 x 4096
+flushed before each call, and with 25% NaN on the missing-value path, unsplit
+and with the history split bfm_autotune picks ("latency_tile"), and the
+largest tile (4096 x 4096
 pixels, N = 512, 10% NaN, p = 8 and 10, float32 and FP16 storage) on the
 missing-value kernel ("config4").  The masked tile and the p = 8 config-4
 tiles are also timed with the MOSUM in FP32 (BFM_PREC_FP32: "masked_fp32",
@@ -564,42 +566,63 @@ def latency_leg(bfm, dev, stream, calls=200, seed=1):
     N = 228, n = 114 (H = 28), k = 3, one call per tile, per-call HIP events.
     Warm: calls back to back on a resident tile.  Cold: before each call the
     L2 caches and the MALL are flushed by writing a 1 GiB buffer (outside the
-    events), so the call reads its 3.7 MB from HBM."""
+    events), so the call reads its 3.7 MB from HBM.  Then the same tile with
+    25% NaN on the missing-value path, warm: one wave per 64 pixels, and the
+    history split that bfm_autotune picks for this tile shape."""
     import torch
 
-    from paper_1807_01751_amd.synth import make_series
+    from paper_1807_01751_amd.synth import apply_missing, make_missing, make_series, split_rate
     Pl, Nl, nl = 4096, 228, 114
     Y, _ = make_series(Pl, Nl, nl, ORDER, seed=seed, device=dev)
     out = {"brk": torch.empty(Pl, dtype=torch.int32, device=dev),
            "mag": torch.empty(Pl, dtype=torch.float32, device=dev)}
     flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    common = dict(n=nl, order=ORDER, freq=FREQ, h=H_FRAC, lam=LAM)
 
     def step():
-        bfm.fit_monitor(Y, n=nl, order=ORDER, freq=FREQ, h=H_FRAC, lam=LAM, outputs=("brk", "mag"),
-                        out_dtype=torch.float32, out=out)
+        bfm.fit_monitor(Y, outputs=("brk", "mag"), out_dtype=torch.float32, out=out, **common)
 
-    res = {}
-    for mode in ("warm", "cold"):
+    def per_call(f, cold):
         for _ in range(10):
-            step()
+            f()
         torch.cuda.synchronize()
         lat = []
         for _ in range(calls):
-            if mode == "cold":
+            if cold:
                 flush.fill_(1.0)
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(stream)
-            step()
+            f()
             b.record(stream)
             b.synchronize()
             lat.append(a.elapsed_time(b))
         lat.sort()
-        q = lambda f: lat[min(len(lat) - 1, int(round(f * (len(lat) - 1))))]
-        res[mode] = {"p50_ms": round(q(0.5), 5), "p99_ms": round(q(0.99), 5), "calls": calls}
-        log(f"bench: latency tile ({mode}) p50 {q(0.5) * 1e3:.1f} us, p99 {q(0.99) * 1e3:.1f} us")
+        q = lambda x: lat[min(len(lat) - 1, int(round(x * (len(lat) - 1))))]
+        return {"p50_ms": round(q(0.5), 5), "p99_ms": round(q(0.99), 5), "calls": calls}
+
+    res = {}
+    for mode in ("warm", "cold"):
+        res[mode] = per_call(step, mode == "cold")
+        log(f"bench: latency tile ({mode}) p50 {res[mode]['p50_ms'] * 1e3:.1f} us, "
+            f"p99 {res[mode]['p99_ms'] * 1e3:.1f} us")
+    r = split_rate(MISSING)
+    Ym = apply_missing(Y.clone(), make_missing(Nl, Pl, iid=r, runs=r, seed=seed + 7, device=dev))
+
+    def mstep():
+        bfm.fit_monitor(Ym, mask_mode=bfm.MASK_NAN, outputs=("brk", "mag"), out_dtype=torch.float32, out=out,
+                        **common)
+
+    bfm.tune_set(Ym, 1, mask_mode=bfm.MASK_NAN, **common)
+    res["masked_warm"] = per_call(mstep, False)
+    split, times = bfm.autotune(Ym, mask_mode=bfm.MASK_NAN, stream=stream, **common)
+    res["masked_warm_tuned"] = {**per_call(mstep, False), "split": split,
+                                "autotune_median_us": {str(k): round(v, 2) for k, v in times.items()}}
+    log(f"bench: latency tile, 25% NaN: p50 {res['masked_warm']['p50_ms'] * 1e3:.1f} us with one wave per "
+        f"64 pixels, {res['masked_warm_tuned']['p50_ms'] * 1e3:.1f} us with the tuned split {split}")
     res["config"] = {"workload": "64x64 = 4096 pixels, N=228 FP32 observations, n=114, k=3 (p=8), "
                                  "h=0.25 (H=28), lambda=2.5, f=23, 20% planted steps; one call per "
-                                 "tile; cold = L2 and MALL flushed by a 1 GiB write before each call"}
+                                 "tile; cold = L2 and MALL flushed by a 1 GiB write before each call; "
+                                 "masked = the same tile with 25% NaN (missing-value path), warm"}
     del flush
     return res
 
