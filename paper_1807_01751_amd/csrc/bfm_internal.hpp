@@ -125,6 +125,8 @@ struct PlainArgs {
 
 hipError_t launch_plain(const PlainArgs& a, int p, hipStream_t stream);
 hipError_t launch_plain_fill(const PlainArgs& a, int p, hipStream_t stream);
+hipError_t launch_plain_export(const PlainArgs& a, int p, hipStream_t stream);
+hipError_t launch_plain_fill_export(const PlainArgs& a, int p, hipStream_t stream);
 
 // Arguments of the period-blocked plain kernel.
 struct PeriodicArgs {

@@ -48,7 +48,9 @@ __global__ __launch_bounds__(256) void fill_status_kernel(const T* __restrict__ 
 
 hipError_t launch_plain(const PlainArgs& a, int p, hipStream_t stream)
 {
-    return a.fill ? launch_plain_fill(a, p, stream) : launch_plain_t<false>(a, p, stream);
+    const bool exp = a.resid || a.mosum;
+    if (a.fill) return exp ? launch_plain_fill_export(a, p, stream) : launch_plain_fill(a, p, stream);
+    return exp ? launch_plain_export(a, p, stream) : launch_plain_t<false, false>(a, p, stream);
 }
 
 hipError_t launch_fill_status(const void* Y, int y_dtype, int64_t ld, int64_t P, int N, int n, int p,

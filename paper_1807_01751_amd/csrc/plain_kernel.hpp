@@ -25,8 +25,9 @@
 // the rows are consumed (footnote of Section 3), and the filled series is
 // monitored.
 //
-// This header holds the kernel template; plain_kernel.hip (as read) and
-// plain_kernel_fill.hip (with filling) instantiate it.
+// This header holds the kernel template; plain_kernel.hip (as read),
+// plain_kernel_fill.hip (with filling) and their _export variants (with
+// per-row exports) instantiate it.
 #pragma once
 
 #include <climits>
@@ -248,32 +249,31 @@ __global__ __launch_bounds__(kPlainBlock) void plain_kernel(PlainArgs a)
     }
 }
 
-template <int NP, bool FILL>
-hipError_t launch_np_fill(const PlainArgs& a, hipStream_t stream)
+template <int NP, bool EXPORT, bool FILL>
+hipError_t launch_np(const PlainArgs& a, hipStream_t stream)
 {
     const dim3 grid((unsigned)((a.P + kPlainBlock - 1) / kPlainBlock));
     const size_t lds = (size_t)a.H * kPlainBlock * sizeof(float);
-    const bool exp = a.resid || a.mosum;
-    if (exp)
-        hipLaunchKernelGGL((plain_kernel<NP, true, FILL>), grid, dim3(kPlainBlock), lds, stream, a);
-    else
-        hipLaunchKernelGGL((plain_kernel<NP, false, FILL>), grid, dim3(kPlainBlock), lds, stream, a);
+    hipLaunchKernelGGL((plain_kernel<NP, EXPORT, FILL>), grid, dim3(kPlainBlock), lds, stream, a);
     return hipGetLastError();
 }
 
-template <bool FILL>
+// The instantiations for p regressors; each (EXPORT, FILL) pair lives in a
+// translation unit of its own (plain_kernel*.hip), so that they compile in
+// parallel.
+template <bool EXPORT, bool FILL>
 hipError_t launch_plain_t(const PlainArgs& a, int p, hipStream_t stream)
 {
     switch (p) {
-    case 2: return launch_np_fill<2, FILL>(a, stream);
-    case 4: return launch_np_fill<4, FILL>(a, stream);
-    case 6: return launch_np_fill<6, FILL>(a, stream);
-    case 8: return launch_np_fill<8, FILL>(a, stream);
-    case 10: return launch_np_fill<10, FILL>(a, stream);
-    case 12: return launch_np_fill<12, FILL>(a, stream);
-    case 14: return launch_np_fill<14, FILL>(a, stream);
-    case 16: return launch_np_fill<16, FILL>(a, stream);
-    case 18: return launch_np_fill<18, FILL>(a, stream);
+    case 2: return launch_np<2, EXPORT, FILL>(a, stream);
+    case 4: return launch_np<4, EXPORT, FILL>(a, stream);
+    case 6: return launch_np<6, EXPORT, FILL>(a, stream);
+    case 8: return launch_np<8, EXPORT, FILL>(a, stream);
+    case 10: return launch_np<10, EXPORT, FILL>(a, stream);
+    case 12: return launch_np<12, EXPORT, FILL>(a, stream);
+    case 14: return launch_np<14, EXPORT, FILL>(a, stream);
+    case 16: return launch_np<16, EXPORT, FILL>(a, stream);
+    case 18: return launch_np<18, EXPORT, FILL>(a, stream);
     default: return hipErrorInvalidValue;
     }
 }

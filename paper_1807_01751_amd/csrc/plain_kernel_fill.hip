@@ -6,7 +6,7 @@ namespace bfm {
 
 hipError_t launch_plain_fill(const PlainArgs& a, int p, hipStream_t stream)
 {
-    return launch_plain_t<true>(a, p, stream);
+    return launch_plain_t<false, true>(a, p, stream);
 }
 
 }  // namespace bfm
