@@ -99,14 +99,12 @@ __device__ __forceinline__ FlaggedObs missing(FlaggedObs o) { return {o.y, 0u}; 
 __device__ __forceinline__ float value(float v) { return v; }
 __device__ __forceinline__ float value(FlaggedObs o) { return o.y; }
 
-// Streams rows [t0, t1) in blocks of F rows aligned to multiples of F, two
-// blocks ahead of the arithmetic in three register buffers used in turn (the
-// loads of a wave must cover the memory latency: the LDS ring limits how many
-// waves share a compute unit).  Every block runs the same unrolled code: a row
-// of the block outside [t0, t1) reads the nearest row inside, is replaced by a
-// missing value before the rows run, and is passed with in = false.
-// init(buf) sees the first block before any row of it runs; pre(tb) runs before
-// the rows of block tb.
+// Streams rows [t0, t1) in blocks of F rows aligned to multiples of F, one
+// block ahead of the arithmetic in two register buffers used in turn.  Every
+// block runs the same unrolled code: a row of the block outside [t0, t1) reads
+// the nearest row inside, is replaced by a missing value before the rows run,
+// and is passed with in = false.  init(buf) sees the first block before any row
+// of it runs; pre(tb) runs before the rows of block tb.
 template <int F, typename At, typename Body, typename Pre, typename Init>
 __device__ __forceinline__ void stream_blocks(At at, int t0, int t1, Body&& body, Pre&& pre, Init&& init)
 {
@@ -133,25 +131,46 @@ __device__ __forceinline__ void stream_blocks(At at, int t0, int t1, Body&& body
 #pragma unroll
         for (int u = 0; u < F; ++u) body(u, tb + u, buf[u], ((in >> u) & 1u) != 0);
     };
-    V a[F], b[F], c[F];
+    // Whole blocks in a straight-line loop with the next block in flight (the
+    // compiler keeps its loads outstanding: no branch between a block's loads
+    // and the previous block's rows); a partial first block runs alone, and
+    // the last blocks go through the general form below.
+    auto load_full = [&](V* buf, int tb) {
+        const auto cur = at(tb);
+#pragma unroll
+        for (int u = 0; u < F; ++u) buf[u] = cur.load(u);
+    };
+    auto run_full = [&](V* buf, int tb) {
+        pre(tb);
+#pragma unroll
+        for (int u = 0; u < F; ++u) body(u, tb + u, buf[u], true);
+    };
+    V a[F], b[F];
     int tb = t0 - t0 % F;
     load(a, tb);
-    if (tb + F < t1) load(b, tb + F);
     init(static_cast<const V*>(a));
-    for (;;) {
-        if (tb + 2 * F < t1) load(c, tb + 2 * F);
+    if (tb < t0 || tb + F > t1) {
         run(a, tb);
         tb += F;
-        if (tb >= t1) break;
-        if (tb + 2 * F < t1) load(a, tb + 2 * F);
-        run(b, tb);
-        tb += F;
-        if (tb >= t1) break;
-        if (tb + 2 * F < t1) load(b, tb + 2 * F);
-        run(c, tb);
-        tb += F;
-        if (tb >= t1) break;
+        if (tb >= t1) return;
+        load(a, tb);
     }
+    for (; tb + 3 * F <= t1; tb += 2 * F) {
+        load_full(b, tb + F);
+        run_full(a, tb);
+        load_full(a, tb + 2 * F);
+        run_full(b, tb + F);
+    }
+    // a holds the block at tb; at most two more blocks follow.
+    if (tb + F < t1) load(b, tb + F);
+    run(a, tb);
+    tb += F;
+    if (tb >= t1) return;
+    if (tb + F < t1) load(a, tb + F);
+    run(b, tb);
+    tb += F;
+    if (tb >= t1) return;
+    run(a, tb);
 }
 
 // Rows tb, tb + 1, ... of the series from one buffer resource based at row tb:
