@@ -122,3 +122,32 @@ def test_masked_autotune_and_limits(bfm, orc):
         bfm.autotune(Y, n=114, mask_mode=bfm.MASK_EXPLICIT)
     assert e.value.code == bfm.E_UNSUPPORTED
     bfm.tune_set(Y, 1, n=114, mask_mode=bfm.MASK_NAN)
+
+
+@pytest.mark.parametrize("split", [2, 4])
+def test_masked_split_bf16_storage(bfm, orc, split):
+    """BF16 storage: the values decode exactly, so the FP64 bar holds."""
+    say(f"case masked split={split} bf16 P=1200 N=400 n=200")
+    Y, _ = masked_series(1200, 400, 200, 3, 330, 0.25, 23.0, torch.bfloat16)
+    kw = dict(n=200, order=3, freq=23.0)
+    bfm.tune_set(Y, split, mask_mode=bfm.MASK_NAN, **kw)
+    g = to_numpy(bfm.fit_monitor(Y, mask_mode=bfm.MASK_NAN, outputs=ALL, **kw))
+    bfm.tune_set(Y, 1, mask_mode=bfm.MASK_NAN, **kw)
+    Yh = Y.float().cpu().numpy()
+    o = orc.fit_monitor(Yh, n=200, order=3, mask_mode=orc.MASK_NAN, threads=0)
+    say("bf16 vs oracle", compare(g, o, lam=2.5, n_v=used_history(Yh, 200)))
+
+
+def test_masked_split_fp32_mosum(bfm, orc):
+    """BFM_PREC_FP32 with a history split, at the FP32 bar against the oracle."""
+    from test_gpu_fp32 import check32
+    say("case masked split=4 fp32 MOSUM P=1500 N=400 n=200")
+    Y, _ = masked_series(1500, 400, 200, 3, 331, 0.25, 23.0)
+    kw = dict(n=200, order=3, freq=23.0)
+    bfm.tune_set(Y, 4, mask_mode=bfm.MASK_NAN, **kw)
+    g = to_numpy(bfm.fit_monitor(Y, mask_mode=bfm.MASK_NAN, outputs=("brk", "mag", "sigma", "status", "mosum"),
+                                 precision="fp32", **kw))
+    bfm.tune_set(Y, 1, mask_mode=bfm.MASK_NAN, **kw)
+    Yh = Y.cpu().numpy()
+    o = orc.fit_monitor(Yh, n=200, order=3, mask_mode=orc.MASK_NAN, threads=0)
+    say("fp32 split vs oracle", check32(g, o, 2.5, used_history(Yh, 200)))
