@@ -239,8 +239,10 @@ int bfm_fit_monitor_typed(bfm_ctx *ctx, const bfm_params *prm, const void *Y, in
  * their partial sums on in wave order, and the last wave fits and monitors
  * (its window's observations taken from the earlier shares where its own share
  * holds fewer than H).  A split needs a block of f history rows per wave and
- * LDS for every wave's window ring plus the staging of the sums; by default
- * the split is 1.
+ * LDS for every wave's window ring plus the staging of the sums.  Untuned, the
+ * missing-value path takes 4 waves per 64 pixels for a tile of at most one
+ * wave per compute unit, 2 up to four waves per compute unit, else 1 (halved
+ * while it does not fit).
  * bfm_autotune times every split that fits (on Y, with scratch outputs,
  * synchronising `stream`; on the missing-value path the BFM_MASK_NAN mode only,
  * as no validity mask is passed) and keeps the fastest for this tile shape (the

@@ -393,14 +393,24 @@ int fit_masked(bfm_ctx* ctx, const bfm_params& p, const void* Y, int y_dtype, in
         return fail(BFM_E_UNSUPPORTED, "a 16-bit series needs f in {12, 23, 24}, n_hist <= %d and "
                     "ld * 4 * f < 2^31 on the missing-value path", bfm::kMaskedPeriodicMaxHist);
     // History split of the period-blocked kernel: the tuned (or pinned) choice
-    // for this tile shape, else one wave per 64 pixels.
+    // for this tile shape, else a rule taken from timings on MI355X (25% NaN,
+    // k = 3): four waves per 64 pixels for a tile of at most one wave per
+    // compute unit (4096 x 228: -8%, 4096 and 16384 x 1000: -20%), two up to
+    // four waves per compute unit (65536 x 400: -8%), else one (a full tile
+    // loses occupancy to the larger workgroup LDS).  A split that does not fit
+    // (LDS, a block of history rows per wave) is halved until it does.
     int split = 1;
     if (blocked) {
         auto tt = ctx->tune.find(tune_key(p, y_dtype, P, ops.cap, ops.F));
-        if (tt != ctx->tune.end()) split = tt->second;
-        if (split > (p.n_hist + ops.F - 1) / ops.F ||
-            bfm::masked_periodic_lds_bytes(ops.cap, ops.F, split) > ctx->max_lds)
-            split = 1;
+        if (tt != ctx->tune.end()) {
+            split = tt->second;
+        } else {
+            const int64_t waves = (P + 63) / 64;
+            split = waves <= ctx->cus ? 4 : (waves <= 4 * (int64_t)ctx->cus ? 2 : 1);
+        }
+        while (split > 1 && (split > (p.n_hist + ops.F - 1) / ops.F ||
+                             bfm::masked_periodic_lds_bytes(ops.cap, ops.F, split) > ctx->max_lds))
+            split /= 2;
     }
     const size_t lds = blocked ? bfm::masked_periodic_lds_bytes(ops.cap, ops.F, split)
                                : bfm::masked_lds_bytes(ops.cap);
