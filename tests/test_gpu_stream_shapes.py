@@ -74,9 +74,9 @@ def test_table_kernel_fill_stream_shapes(bfm, orc, N, n, hw):
 
 
 MASKED_SHAPES = [pytest.param(*SHAPES[0], marks=pytest.mark.xfail(
-    reason="general missing-value kernel on a 20-row history with 5-row windows: magnitude within "
-           "2.6e-9 of the oracle (sigma 2.9e-10), the same with the build before the streaming "
-           "change; outside the 1e-9 bar, cause not found", strict=False))] + SHAPES[1:]
+    reason="general missing-value kernel on a 20-row history with 5-row windows: a pixel with 7 "
+           "observed history rows for 6 coefficients (ill-conditioned normal equations) has its "
+           "magnitude within 2.6e-9 of the oracle, outside the 1e-9 bar", strict=False))] + SHAPES[1:]
 
 
 @pytest.mark.parametrize("N,n,hw", MASKED_SHAPES)
